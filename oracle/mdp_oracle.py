@@ -1,0 +1,381 @@
+"""FP64 CPU oracle for inexact GMRES policy iteration -- TEST INFRASTRUCTURE.
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this module.  The product path (the HIP library and its
+Python binding) never imports, links or calls it, and it shares no code with
+that path: the only thing both consume is the seeded input generator
+(``paper_2211_04299_amd.synth``), which draws inputs and holds none of the
+method's arithmetic.
+
+Everything is float64, plain and unfused; library primitives (a sparse or
+dense matrix-vector product, a dense LU solve, a least-squares solve) serve as
+single steps.  Citations are to the paper (Gargiani, Liao-McPherson, Zanelli,
+Lygeros, "Inexact GMRES Policy Iteration for Large-Scale Markov Decision
+Processes", arXiv:2211.04299).
+
+What each function follows, and what pins it (tests/test_oracle_pins.py):
+
+  q_values, bellman        Bellman operators T^pi, T and GreedyPolicy (Sec. 2,
+                           eqs. 3-4 and the greedy definition).  Pinned by a
+                           hand-computed two-state example (tests/golden),
+                           closed forms (self-loops, uniform transitions,
+                           constant costs) and the contraction, monotonicity and
+                           shift-invariance properties.
+  policy_eval_lu           closed form V^pi = (I - gamma P^pi)^{-1} g^pi
+                           (Sec. 2.1).  Pinned by the Neumann series, Lemma 3's
+                           equality case and a hand-solved two-state chain.
+  policy_iteration         PI (Sec. 2.1).  Pinned by brute force over all
+                           policies (eq. 2) and agreement with value iteration.
+  value_iteration          VI, eq. 6 with its gamma-contraction stopping bound.
+  brute_force              V* = componentwise min over all deterministic
+                           policies (eq. 2).
+  gmres_inner, igmres_pi   Algorithm 2 (GMRES(W) policy iteration) in the
+                           paper's order, with the readings listed below.
+                           Pinned by the GMRES minimum-residual property
+                           (eq. 13) computed from an explicitly formed Krylov
+                           matrix, by agreement with LU at alpha -> 0, and by
+                           agreement of the returned V with PI-LU's V*.
+  opi                      optimistic PI with a fixed number of VI sweeps
+                           (Sec. 2.1); OPI(1) is VI.
+  certificate              ||V - V*||_inf <= ||TV - V||_inf / (1 - gamma),
+                           from gamma-contraction (Sec. 2).
+
+Readings where the paper is silent or garbled (each is also listed in the
+design notes of the repository):
+  * ties in GreedyPolicy: lowest action index; PI's improvement keeps the
+    incumbent action unless another is better by more than
+    1e-12 * max(1, ||V||_inf);
+  * outer termination of Algorithm 2: first k with ||T V_k - V_k||_inf <= tol
+    (the algorithm itself runs a fixed K);
+  * "||Phi||_2" in the least-squares step after a restart is the 2-norm of the
+    residual that produced the current first basis vector, and the update
+    "V_{k+1} <- Q y + V_k" adds to the iterate at the start of the current
+    restart cycle;
+  * "go to line 35" ends the inner loop and proceeds to the next outer step;
+  * Phi_k = 0 (or a zero restart residual) means the inner loop is not entered;
+  * the least-squares problem uses the leading (i+1) x i block of H;
+  * infinity-norm in every stopping test, 2-norm inside GMRES.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "q_values", "bellman", "greedy_keep", "policy_cost", "policy_matrix_dense",
+    "policy_matrix_sparse", "j_apply", "policy_eval_lu", "policy_eval_neumann",
+    "policy_iteration", "value_iteration", "brute_force", "gmres_inner",
+    "igmres_pi", "opi", "certificate", "action_gaps", "OracleStats",
+]
+
+
+# ---------------------------------------------------------------------------
+# operators (Section 2)
+# ---------------------------------------------------------------------------
+
+def _P_rows(mdp):
+    """The (n*m) x n transition matrix, row r = s*m + a holds P(s, a, .)."""
+    n, m = mdp.n, mdp.m
+    if mdp.fmt == "dense":
+        return mdp.P.reshape(n * m, n)
+    return sp.csr_matrix((np.asarray(mdp.val, np.float64), mdp.col, mdp.row_ptr),
+                         shape=(n * m, n))
+
+
+def q_values(mdp, V):
+    """Q[s, a] = g(s, a) + gamma * sum_s' p_ss'(a) V(s')   (the expression
+    minimised in the Bellman equation for V*, eq. 4, and in GreedyPolicy)."""
+    V = np.asarray(V, dtype=np.float64)
+    EV = _P_rows(mdp) @ V
+    return (np.asarray(mdp.cost, np.float64) + mdp.gamma * EV).reshape(mdp.n, mdp.m)
+
+
+def bellman(mdp, V):
+    """T V, a greedy policy w.r.t. V (lowest action index on exact ties) and
+    the Bellman residual ||T V - V||_inf  (operators T and GreedyPolicy of
+    Section 2; residual function r(V) = V - T V, eq. 8)."""
+    Q = q_values(mdp, V)
+    pi = np.argmin(Q, axis=1).astype(np.int32)  # first minimiser
+    TV = Q[np.arange(mdp.n), pi]
+    return TV, pi, float(np.max(np.abs(TV - V))) if mdp.n else 0.0
+
+
+def action_gaps(mdp, V):
+    """Per state: second-smallest minus smallest Q-value (inf if m == 1)."""
+    Q = np.sort(q_values(mdp, V), axis=1)
+    if mdp.m == 1:
+        return np.full(mdp.n, np.inf)
+    return Q[:, 1] - Q[:, 0]
+
+
+def greedy_keep(mdp, V, pi_old, rel_tie=1e-12):
+    """Policy improvement that keeps the incumbent action unless another action
+    is better by more than rel_tie * max(1, ||V||_inf)."""
+    Q = q_values(mdp, V)
+    best = np.argmin(Q, axis=1)
+    idx = np.arange(mdp.n)
+    tie = rel_tie * max(1.0, float(np.max(np.abs(V))) if mdp.n else 1.0)
+    keep = Q[idx, pi_old] <= Q[idx, best] + tie
+    return np.where(keep, pi_old, best).astype(np.int32)
+
+
+def policy_cost(mdp, pi):
+    """g^pi(s) = g(s, pi(s))."""
+    return np.asarray(mdp.cost, np.float64).reshape(mdp.n, mdp.m)[np.arange(mdp.n), pi]
+
+
+def policy_matrix_sparse(mdp, pi):
+    """[P^pi]_{s s'} = p_ss'(pi(s)) as a sparse matrix."""
+    rows = np.arange(mdp.n) * mdp.m + np.asarray(pi)
+    return _P_rows(mdp)[rows]
+
+
+def policy_matrix_dense(mdp, pi):
+    Ppi = policy_matrix_sparse(mdp, pi)
+    return Ppi.toarray() if sp.issparse(Ppi) else np.asarray(Ppi)
+
+
+def j_apply(mdp, pi, x, Ppi=None):
+    """J x = (I - gamma P^pi) x   (Newton matrix, eq. 10)."""
+    if Ppi is None:
+        Ppi = policy_matrix_sparse(mdp, pi)
+    return x - mdp.gamma * (Ppi @ x)
+
+
+def policy_eval_lu(mdp, pi):
+    """V^pi = (I - gamma P^pi)^{-1} g^pi by a dense LU solve (policy
+    evaluation, Section 2.1)."""
+    A = np.eye(mdp.n) - mdp.gamma * policy_matrix_dense(mdp, pi)
+    return np.linalg.solve(A, policy_cost(mdp, pi))
+
+
+def policy_eval_neumann(mdp, pi, rel=1e-15, max_terms=1_000_000):
+    """V^pi = sum_k (gamma P^pi)^k g^pi (the series in the proof of Lemma 3),
+    summed until the next term is below rel * ||partial sum||_inf."""
+    Ppi = policy_matrix_sparse(mdp, pi)
+    term = policy_cost(mdp, pi)
+    V = term.copy()
+    for _ in range(max_terms):
+        term = mdp.gamma * (Ppi @ term)
+        V += term
+        if np.max(np.abs(term)) <= rel * max(np.max(np.abs(V)), 1e-300):
+            break
+    return V
+
+
+# ---------------------------------------------------------------------------
+# plain dynamic programming (Section 2.1, eq. 2)
+# ---------------------------------------------------------------------------
+
+def policy_iteration(mdp, V0=None, max_iter=1000):
+    """Exact PI: pi_0 = GreedyPolicy(V0), then alternate LU evaluation and
+    improvement until the policy repeats.  Returns (V, pi, iterations)."""
+    V = np.zeros(mdp.n) if V0 is None else np.asarray(V0, np.float64)
+    _, pi, _ = bellman(mdp, V)
+    for it in range(1, max_iter + 1):
+        V = policy_eval_lu(mdp, pi)
+        new = greedy_keep(mdp, V, pi)
+        if np.array_equal(new, pi):
+            return V, pi, it
+        pi = new
+    raise RuntimeError("policy iteration did not terminate")
+
+
+def value_iteration(mdp, eps=None, V0=None, max_iter=10_000_000):
+    """VI, V <- T V (eq. 6), until ||V_{j+1} - V_j||_inf <= eps (1-gamma)/gamma,
+    which bounds ||V_{j+1} - V*||_inf by eps (gamma-contraction).  eps defaults
+    to 1e-12 * ||V||_inf.  Returns (V, sweeps)."""
+    V = np.zeros(mdp.n) if V0 is None else np.asarray(V0, np.float64).copy()
+    g = mdp.gamma
+    for j in range(1, max_iter + 1):
+        TV, _, _ = bellman(mdp, V)
+        d = float(np.max(np.abs(TV - V)))
+        V = TV
+        e = eps if eps is not None else 1e-12 * max(float(np.max(np.abs(V))), 1e-300)
+        if d <= e * (1 - g) / g:
+            return V, j
+    raise RuntimeError("value iteration did not converge")
+
+
+def brute_force(mdp, atol=1e-12):
+    """V* = componentwise minimum of V^pi over all m^n deterministic policies
+    (eq. 2).  Returns (V*, list of optimal policies).  Only for tiny MDPs."""
+    n, m = mdp.n, mdp.m
+    if m ** n > 200_000:
+        raise ValueError("too many policies for brute force")
+    vals = {}
+    for pol in itertools.product(range(m), repeat=n):
+        vals[pol] = policy_eval_lu(mdp, np.array(pol, dtype=np.int32))
+    Vstar = np.min(np.stack(list(vals.values())), axis=0)
+    opt = [np.array(p, dtype=np.int32) for p, v in vals.items()
+           if np.all(v <= Vstar + atol * max(1.0, np.max(np.abs(Vstar))))]
+    return Vstar, opt
+
+
+def certificate(mdp, V):
+    """Upper bound on ||V - V*||_inf from one Bellman pass:
+    ||V - V*|| <= ||V - TV|| + ||TV - TV*|| <= ||V - TV|| + gamma ||V - V*||."""
+    _, _, res = bellman(mdp, V)
+    return res / (1.0 - mdp.gamma)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2: GMRES(W) policy iteration
+# ---------------------------------------------------------------------------
+
+@dataclass
+class OracleStats:
+    outer: int = 0
+    inner: int = 0
+    restarts: int = 0
+    breakdowns: int = 0
+    inner_per_outer: list = field(default_factory=list)
+    res_history: list = field(default_factory=list)
+    converged: bool = False
+
+
+def _lsq(H, i, beta):
+    """argmin_y || beta e_1 - H[:i+1, :i] y ||_2  (leading block of H)."""
+    rhs = np.zeros(i + 1)
+    rhs[0] = beta
+    y, *_ = np.linalg.lstsq(H[:i + 1, :i], rhs, rcond=None)
+    return y
+
+
+def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=False):
+    """The inner while-loop of Algorithm 2 for J = I - gamma P^pi, b = g^pi.
+
+    Starting at x0, runs restarted GMRES(W) (Arnoldi with modified
+    Gram-Schmidt, a least-squares solve on the Hessenberg matrix, explicit
+    residual test every step) until
+        || b - J x ||_inf <= alpha * ref_inf,
+    where ref_inf defaults to ||b - J x0||_inf (= ||Phi_k||_inf).
+    Two guards the paper leaves implicit end the loop early: max_inner
+    Arnoldi steps, and a whole restart cycle that lowers the residual 2-norm
+    (the quantity GMRES minimises) by less than a factor 1 - 1e-6: restarted
+    GMRES(W) with W < n can stagnate completely, and rounding puts a floor
+    under the residual.
+    Returns (x, info) with info = dict(steps, restarts, breakdown, H_first,
+    iterates (if trace), res_inf).
+    """
+    n = mdp.n
+    Ppi = policy_matrix_sparse(mdp, pi)
+    b = policy_cost(mdp, pi)
+    J = lambda v: j_apply(mdp, pi, v, Ppi)  # noqa: E731
+
+    x_cycle = np.asarray(x0, np.float64).copy()   # iterate at the cycle start
+    x = x_cycle.copy()
+    r = b - J(x)
+    if ref_inf is None:
+        ref_inf = float(np.max(np.abs(r)))
+    thr = alpha * ref_inf
+    beta = float(np.linalg.norm(r))
+    Q = np.zeros((n, W + 1))
+    H = np.zeros((W + 1, W))
+    if beta > 0:
+        Q[:, 0] = r / beta
+    i = 0          # number of Arnoldi columns built in this cycle
+    steps = restarts = 0
+    breakdown = False
+    H_first = None
+    iterates = []
+    res_inf = float(np.max(np.abs(r)))
+    stagnated = False
+    while res_inf > thr and steps < max_inner:
+        q = J(Q[:, i])
+        for j in range(i + 1):                    # modified Gram-Schmidt
+            H[j, i] = Q[:, j] @ q
+            q = q - H[j, i] * Q[:, j]
+        H[i + 1, i] = np.linalg.norm(q)
+        steps += 1
+        if H[i + 1, i] == 0.0:                    # lucky breakdown
+            y = _lsq(H, i + 1, beta)
+            x = x_cycle + Q[:, :i + 1] @ y
+            breakdown = True
+            res_inf = float(np.max(np.abs(b - J(x))))
+            if trace:
+                iterates.append(x.copy())
+            break
+        Q[:, i + 1] = q / H[i + 1, i]
+        y = _lsq(H, i + 1, beta)
+        x = x_cycle + Q[:, :i + 1] @ y
+        if trace and restarts == 0:
+            iterates.append(x.copy())
+        r = b - J(x)
+        res_inf = float(np.max(np.abs(r)))
+        if i + 1 == W:                            # restart from the new residual
+            if restarts == 0:
+                H_first = H.copy()
+            restarts += 1
+            Q[:] = 0.0
+            H[:] = 0.0
+            beta_prev = beta
+            beta = float(np.linalg.norm(r))
+            if beta > 0:
+                Q[:, 0] = r / beta
+            x_cycle = x.copy()
+            i = 0
+            if res_inf > thr and beta > (1.0 - 1e-6) * beta_prev:
+                stagnated = True
+                break
+        else:
+            i += 1
+    if H_first is None:
+        H_first = H.copy()
+    return x, dict(steps=steps, restarts=restarts, breakdown=breakdown, H_first=H_first,
+                   iterates=iterates, res_inf=res_inf, thr=thr, stagnated=stagnated)
+
+
+def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inner=10_000):
+    """Algorithm 2 with outer termination at ||T V_k - V_k||_inf <= tol.
+
+    alpha defaults to the midpoint of Theorem 1's admissible range,
+    0.5 * (1 - gamma) / (1 + gamma).  Returns (V, pi, OracleStats); V and pi
+    are V_k and GreedyPolicy(V_k) of the terminating outer step.
+    """
+    g = mdp.gamma
+    if alpha is None:
+        alpha = 0.5 * (1 - g) / (1 + g)
+    V = np.zeros(mdp.n) if V0 is None else np.asarray(V0, np.float64).copy()
+    st = OracleStats()
+    for k in range(max_outer):
+        TV, pi, res = bellman(mdp, V)
+        st.res_history.append(res)
+        if res <= tol:
+            st.converged = True
+            st.outer = k
+            return V, pi, st
+        Phi = policy_cost(mdp, pi) - j_apply(mdp, pi, V)
+        V, info = gmres_inner(mdp, pi, V, alpha, W, max_inner,
+                              ref_inf=float(np.max(np.abs(Phi))))
+        st.inner += info["steps"]
+        st.restarts += info["restarts"]
+        st.breakdowns += int(info["breakdown"])
+        st.inner_per_outer.append(info["steps"])
+    TV, pi, res = bellman(mdp, V)
+    st.outer = max_outer
+    st.converged = res <= tol
+    return V, pi, st
+
+
+def opi(mdp, sweeps, tol=1e-8, V0=None, max_outer=10_000_000):
+    """Optimistic PI: greedy policy from V_k, then `sweeps` applications of
+    T^{pi_k} (the first of which equals T V_k); stop at ||T V - V||_inf <= tol.
+    Returns (V, pi, outer, total_sweeps)."""
+    V = np.zeros(mdp.n) if V0 is None else np.asarray(V0, np.float64).copy()
+    total = 0
+    for k in range(max_outer):
+        TV, pi, res = bellman(mdp, V)
+        if res <= tol:
+            return V, pi, k, total
+        Ppi = policy_matrix_sparse(mdp, pi)
+        gpi = policy_cost(mdp, pi)
+        V = TV
+        total += 1
+        for _ in range(sweeps - 1):
+            V = gpi + mdp.gamma * (Ppi @ V)
+            total += 1
+    raise RuntimeError("OPI did not converge")

@@ -1,0 +1,274 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics
+(not against the oracle itself): a hand-solved example, closed forms,
+operator properties (Section 2), Lemmas 1-3, brute force over all policies
+(eq. 2), and the GMRES minimum-residual property (eq. 13)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mdp_oracle as O
+from paper_2211_04299_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def two_state():
+    d = json.load(open(os.path.join(GOLD, "two_state.json")))
+    mdp = synth.from_rows(d["n"], d["m"], d["gamma"], [[tuple(e) for e in r] for r in d["rows"]],
+                          d["cost"])
+    return mdp, d
+
+
+# ---------------------------------------------------------------- hand example
+
+def test_two_state_bellman_and_greedy():
+    mdp, d = two_state()
+    V = np.array(d["V"])
+    np.testing.assert_allclose(O.q_values(mdp, V), d["Q_of_V"], rtol=0, atol=1e-15)
+    TV, pi, res = O.bellman(mdp, V)
+    np.testing.assert_allclose(TV, d["TV"], rtol=0, atol=1e-15)
+    assert pi.tolist() == d["greedy"]
+    assert res == pytest.approx(d["res_inf"], abs=1e-15)
+
+
+def test_two_state_policy_values_and_optimum():
+    mdp, d = two_state()
+    for key, want in d["V_pi"].items():
+        pi = np.array([int(x) for x in key.split(",")], dtype=np.int32)
+        np.testing.assert_allclose(O.policy_eval_lu(mdp, pi), want, rtol=1e-14)
+        np.testing.assert_allclose(O.policy_eval_neumann(mdp, pi), want, rtol=1e-13)
+    Vs, opt = O.brute_force(mdp)
+    np.testing.assert_allclose(Vs, d["V_star"], rtol=1e-14)
+    assert [p.tolist() for p in opt] == [d["pi_star"]]
+    V, pi, _ = O.policy_iteration(mdp)
+    np.testing.assert_allclose(V, d["V_star"], rtol=1e-14)
+    assert pi.tolist() == d["pi_star"]
+    V, _ = O.value_iteration(mdp)
+    np.testing.assert_allclose(V, d["V_star"], rtol=1e-11)
+    V, pi, st = O.igmres_pi(mdp, W=2, tol=1e-13)
+    np.testing.assert_allclose(V, d["V_star"], rtol=1e-12)
+    assert st.converged
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("gamma", [0.5, 0.9, 0.99])
+def test_constant_cost_lemma3_equality(gamma):
+    # g == c0 gives V^pi = c0/(1-gamma) 1 for every policy (row-stochastic P^pi)
+    mdp = synth.sparse_uniform(60, 3, 4, gamma, seed=3)
+    mdp.cost = np.full(mdp.n * mdp.m, 0.7)
+    want = np.full(mdp.n, 0.7 / (1 - gamma))
+    pi = np.random.default_rng(0).integers(0, 3, size=60).astype(np.int32)
+    np.testing.assert_allclose(O.policy_eval_lu(mdp, pi), want, rtol=1e-12)
+    V, _, _ = O.policy_iteration(mdp)
+    np.testing.assert_allclose(V, want, rtol=1e-12)
+    V, _, _ = O.igmres_pi(mdp, W=5, tol=1e-12 * want[0])
+    np.testing.assert_allclose(V, want, rtol=1e-11)
+
+
+def test_self_loops_closed_form():
+    mdp = synth.self_loops(30, 4, 0.9, seed=1)
+    cmin = mdp.cost.reshape(30, 4).min(axis=1)
+    want = cmin / (1 - 0.9)
+    V, pi, _ = O.policy_iteration(mdp)
+    np.testing.assert_allclose(V, want, rtol=1e-13)
+    assert np.array_equal(pi, mdp.cost.reshape(30, 4).argmin(axis=1))
+    V, _ = O.value_iteration(mdp)
+    np.testing.assert_allclose(V, want, rtol=1e-10)
+
+
+def test_uniform_transitions_closed_form_and_breakdown():
+    n, m, g = 25, 3, 0.95
+    mdp = synth.uniform_transitions(n, m, g, seed=2)
+    cmin = mdp.cost.reshape(n, m).min(axis=1)
+    want = cmin + g / (1 - g) * cmin.mean()
+    V, pi, _ = O.policy_iteration(mdp)
+    np.testing.assert_allclose(V, want, rtol=1e-13)
+    # J = I - gamma/n 11^T: the Krylov space of any residual has dimension <= 2
+    pi = np.zeros(n, dtype=np.int32)
+    x, info = O.gmres_inner(mdp, pi, np.zeros(n), alpha=1e-14, W=10)
+    assert info["steps"] <= 2
+    np.testing.assert_allclose(x, O.policy_eval_neumann(mdp, pi), rtol=1e-12)
+
+
+def test_cycle_closed_form():
+    # single action, deterministic n-cycle: V(s) = sum_t gamma^t c(s+t) / (1 - gamma^n)
+    n, g = 7, 0.8
+    mdp = synth.cyclic(n, 1, g, seed=4)
+    c = mdp.cost
+    want = np.array([sum(g ** t * c[(s + t) % n] for t in range(n)) / (1 - g ** n)
+                     for s in range(n)])
+    np.testing.assert_allclose(O.policy_eval_lu(mdp, np.zeros(n, np.int32)), want, rtol=1e-13)
+    # GMRES needs the full Krylov dimension n here (Lemma 1: spectrum on a circle)
+    x, info = O.gmres_inner(mdp, np.zeros(n, np.int32), np.zeros(n), alpha=1e-13, W=n)
+    np.testing.assert_allclose(x, want, rtol=1e-11)
+    assert info["steps"] == n
+
+
+def test_tie_rule_lowest_index():
+    # actions 0 and 2 identical and best; GreedyPolicy must return 0
+    rows, cost = [], []
+    for s in range(3):
+        rows += [[(s, 1.0)], [((s + 1) % 3, 1.0)], [(s, 1.0)]]
+        cost += [0.1, 0.5, 0.1]
+    mdp = synth.from_rows(3, 3, 0.9, rows, cost)
+    _, pi, _ = O.bellman(mdp, np.zeros(3))
+    assert pi.tolist() == [0, 0, 0]
+    # PI keeps the incumbent on a tie
+    newpi = O.greedy_keep(mdp, np.full(3, 1.0), np.array([2, 0, 2], np.int32))
+    assert newpi.tolist() == [2, 0, 2]
+
+
+# ---------------------------------------------------------------- properties
+
+@pytest.fixture(scope="module")
+def small():
+    return synth.sparse_uniform(80, 4, 6, 0.9, seed=11)
+
+
+def test_operator_properties(small):
+    rng = np.random.default_rng(5)
+    g = small.gamma
+    for _ in range(5):
+        V1, V2 = rng.normal(size=80) * 3, rng.normal(size=80) * 3
+        T1, _, _ = O.bellman(small, V1)
+        T2, _, _ = O.bellman(small, V2)
+        assert np.max(np.abs(T1 - T2)) <= g * np.max(np.abs(V1 - V2)) * (1 + 1e-12)   # contraction
+        r1, r2 = V1 - T1, V2 - T2
+        assert np.max(np.abs(r1 - r2)) <= (1 + g) * np.max(np.abs(V1 - V2)) * (1 + 1e-12)  # Lemma 2
+        Tup, _, _ = O.bellman(small, np.maximum(V1, V2))
+        assert np.all(Tup >= np.maximum(T1, T2) - 1e-13)                           # monotone
+        c = rng.normal()
+        Ts, _, _ = O.bellman(small, V1 + c)
+        np.testing.assert_allclose(Ts, T1 + g * c, rtol=0, atol=1e-13)             # shift
+
+
+def test_lemma1_and_lemma3(small):
+    g = small.gamma
+    pi = np.random.default_rng(1).integers(0, 4, size=80).astype(np.int32)
+    A = np.eye(80) - g * O.policy_matrix_dense(small, pi)
+    ev = np.linalg.eigvals(A)
+    assert np.all(np.abs(ev - 1.0) <= g * (1 + 1e-10))
+    Ainv = np.linalg.inv(A)
+    assert np.max(np.abs(Ainv).sum(axis=1)) == pytest.approx(1 / (1 - g), rel=1e-12)
+
+
+def test_neumann_matches_lu(small):
+    pi = np.random.default_rng(2).integers(0, 4, size=80).astype(np.int32)
+    np.testing.assert_allclose(O.policy_eval_lu(small, pi), O.policy_eval_neumann(small, pi),
+                               rtol=1e-12)
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_agrees_with_pi_vi(seed):
+    rng = np.random.default_rng(seed)
+    n, m = int(rng.integers(2, 7)), int(rng.integers(1, 4))
+    mdp = synth.random_micro(n, m, float(rng.choice([0.5, 0.9, 0.99])), seed=seed)
+    Vb, opt = O.brute_force(mdp)
+    Vp, pip, _ = O.policy_iteration(mdp)
+    np.testing.assert_allclose(Vp, Vb, rtol=1e-12)
+    assert any(np.array_equal(pip, p) for p in opt)
+    Vv, _ = O.value_iteration(mdp)
+    np.testing.assert_allclose(Vv, Vb, rtol=1e-10)
+    TV, _, _ = O.bellman(mdp, Vb)
+    np.testing.assert_allclose(TV, Vb, rtol=1e-13)                 # V* = T V*
+    # GMRES(W) with W >= n is exact within one cycle (at most n steps, Sec. 2.2)
+    Vg, pig, st = O.igmres_pi(mdp, W=n, tol=1e-11 * max(1.0, float(np.max(np.abs(Vb)))))
+    np.testing.assert_allclose(Vg, Vb, rtol=1e-10)
+    assert st.converged
+
+
+# ---------------------------------------------------------------- GMRES
+
+def test_gmres_minimum_residual_property():
+    """x_i = argmin ||b - J x||_2 over x0 + K_i (eq. 13), K_i spanned by the
+    explicitly formed Krylov matrix [r0, J r0, ..., J^{i-1} r0]."""
+    mdp = synth.sparse_uniform(40, 3, 5, 0.95, seed=7)
+    pi = np.random.default_rng(3).integers(0, 3, size=40).astype(np.int32)
+    x0 = np.random.default_rng(4).normal(size=40)
+    _, info = O.gmres_inner(mdp, pi, x0, alpha=1e-15, W=8, trace=True, max_inner=6)
+    b = O.policy_cost(mdp, pi)
+    J = lambda v: O.j_apply(mdp, pi, v)  # noqa: E731
+    r0 = b - J(x0)
+    K = [r0 / np.linalg.norm(r0)]
+    for i, xi in enumerate(info["iterates"], start=1):
+        Km = np.stack(K, axis=1)
+        JK = np.stack([J(v) for v in K], axis=1)
+        c, *_ = np.linalg.lstsq(JK, r0, rcond=None)
+        want = x0 + Km @ c
+        np.testing.assert_allclose(xi, want, rtol=1e-9, atol=1e-9)
+        nxt = J(K[-1])
+        K.append(nxt / np.linalg.norm(nxt))
+
+
+@pytest.mark.parametrize("W", [1, 2, 5, 40])
+def test_gmres_restarted_converges_to_lu(W):
+    mdp = synth.sparse_uniform(50, 3, 5, 0.9, seed=8)
+    pi = np.random.default_rng(9).integers(0, 3, size=50).astype(np.int32)
+    x, info = O.gmres_inner(mdp, pi, np.zeros(50), alpha=1e-13, W=W)
+    np.testing.assert_allclose(x, O.policy_eval_lu(mdp, pi), rtol=1e-11)
+    if W < 10:
+        assert info["restarts"] >= 1
+
+
+def test_gmres_stagnation_guard_ends_inner_loop():
+    # restarted GMRES(3) stagnates completely on this 4-state system
+    mdp = synth.random_micro(4, 2, 0.99, seed=1)
+    pi = np.array([1, 0, 0, 1], np.int32)
+    V = np.array([-4.86186671, -5.50835827, -4.59732929, -5.18435778])
+    x, info = O.gmres_inner(mdp, pi, V, alpha=1e-3, W=3)
+    assert info["stagnated"] and info["steps"] < 100
+    x, info = O.gmres_inner(mdp, pi, V, alpha=1e-3, W=4)
+    assert not info["stagnated"] and info["res_inf"] <= info["thr"]
+
+
+def test_gmres_inexact_rule_holds():
+    mdp = synth.sparse_uniform(200, 4, 6, 0.99, seed=10)
+    pi = np.zeros(200, np.int32)
+    x0 = np.zeros(200)
+    b = O.policy_cost(mdp, pi)
+    r0 = np.max(np.abs(b - O.j_apply(mdp, pi, x0)))
+    for alpha in (0.5, 0.1, 1e-3):
+        x, info = O.gmres_inner(mdp, pi, x0, alpha=alpha, W=10)
+        r = np.max(np.abs(b - O.j_apply(mdp, pi, x)))
+        assert r <= alpha * r0
+        # and it stopped at the first step that satisfied the rule
+        if info["steps"] > 1:
+            _, info2 = O.gmres_inner(mdp, pi, x0, alpha=alpha, W=10, max_inner=info["steps"] - 1)
+            assert info2["res_inf"] > alpha * r0
+
+
+def test_igmres_pi_matches_pi_lu_c1():
+    mdp = synth.config("c1", seed=0)
+    Vs, pis, _ = O.policy_iteration(mdp)
+    V, pi, st = O.igmres_pi(mdp, W=20, tol=1e-11)
+    assert st.converged
+    assert np.max(np.abs(V - Vs)) / np.max(np.abs(Vs)) <= 1e-10
+    gaps = O.action_gaps(mdp, Vs)
+    assert np.array_equal(pi[gaps > 1e-9], pis[gaps > 1e-9])
+    assert O.certificate(mdp, V) >= np.max(np.abs(V - Vs))
+
+
+def test_opi_one_sweep_is_vi(small):
+    # OPI with one sweep per outer step is VI (Section 2.1): same stopping index
+    tol = 1e-6
+    Vo, _, outer, total = O.opi(small, 1, tol=tol)
+    assert total == outer
+    g = small.gamma
+    Vv, sweeps = O.value_iteration(small, eps=tol * g / (1 - g))
+    # VI stops one application later (it tests the step it just took)
+    assert sweeps == outer + 1
+    TVo, _, _ = O.bellman(small, Vo)
+    np.testing.assert_array_equal(TVo, Vv)
+
+
+def test_certificate_bounds_error(small):
+    Vs, _, _ = O.policy_iteration(small)
+    rng = np.random.default_rng(12)
+    for scale in (1e-2, 1e-5, 1e-9):
+        V = Vs + scale * rng.normal(size=small.n)
+        assert np.max(np.abs(V - Vs)) <= O.certificate(small, V) * (1 + 1e-9) + 1e-15
