@@ -1,0 +1,224 @@
+/*
+ * igmres.h -- C-ABI of the MI355X (gfx950) inexact GMRES policy iteration
+ * library, libigmres.so.
+ *
+ * The method is the one of Gargiani, Liao-McPherson, Zanelli and Lygeros,
+ * "Inexact GMRES Policy Iteration for Large-Scale Markov Decision Processes"
+ * (arXiv:2211.04299): finite discounted-cost MDPs {S, A, P, g, gamma}
+ * (Section 2), the Bellman operators T^pi, T and GreedyPolicy (Section 2),
+ * policy evaluation V^pi = (I - gamma P^pi)^{-1} g^pi, and Algorithm 2
+ * (GMRES(W) policy iteration) with the inexact stopping rule of eq. 11 in the
+ * infinity-norm.
+ *
+ * Conventions
+ *   - States and actions are 0-based.  Row r = s*m + a of the transition data
+ *     holds P(s, a, .); cost[s*m + a] = g(s, a).  Every state has all m
+ *     actions.
+ *   - Vectors passed to the solver entry points (V, TV, pi) are DEVICE
+ *     pointers owned by the caller (e.g. torch tensors); work is enqueued on
+ *     the caller's HIP stream `stream` (hipStream_t passed as void*, NULL =
+ *     the null stream).  Solver calls return after the solve has finished on
+ *     that stream; bellman_apply is stream-ordered and returns immediately.
+ *   - The MDP handle owns a device copy of P and g (re-laid-out for the
+ *     GPU) plus all solver workspace; the caller may free its own arrays when
+ *     mdp_create returns.  A handle is not re-entrant: calls on one handle
+ *     must not overlap.  Distinct handles are independent.
+ *   - Every entry point returns an ig_status; nothing throws across the ABI.
+ *     On IG_E_INVALID outputs are untouched.  ig_last_error() returns a
+ *     thread-local description of the last failure.
+ */
+#ifndef IGMRES_H
+#define IGMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IG_OK = 0,
+  IG_E_INVALID = -1,   /* bad argument or malformed MDP; nothing was written */
+  IG_E_NOMEM = -2,     /* device or host allocation failed                   */
+  IG_E_DEVICE = -3,    /* a HIP call failed                                  */
+  IG_E_NOCONV = -4,    /* iteration cap reached; last iterate and stats kept */
+  IG_E_NUMERIC = -5,   /* NaN or Inf met in a Bellman pass                   */
+  IG_E_TOO_LARGE = -6  /* request exceeds a capacity (restart > IG_MAX_RESTART,
+                          serving budget)                                     */
+} ig_status;
+
+typedef enum { IG_FMT_CSR = 0, IG_FMT_DENSE = 1 } ig_format;
+typedef enum { IG_FP64 = 0, IG_FP32 = 1, IG_BF16 = 2 } ig_dtype;
+/* FP64: every vector and product in double.  MIXED: Krylov basis and the
+ * P^pi products inside GMRES in single precision with float accumulation;
+ * Bellman passes, residuals, dot products, the solution update and the
+ * Hessenberg/Givens solve stay double. */
+typedef enum { IG_MODE_FP64 = 0, IG_MODE_MIXED = 1 } ig_mode;
+
+#define IG_MAX_RESTART 128
+
+/* MDP description (problem setting, Section 2).
+ *   fmt == IG_FMT_CSR:   row_ptr int64[n*m+1] (row_ptr[0] == 0, nondecreasing,
+ *                        every row non-empty), col int32[nnz] in [0, n) with
+ *                        no repeats inside a row, val[nnz] probabilities.
+ *   fmt == IG_FMT_DENSE: val[n*m*n], val[(s*m + a)*n + s'] = P(s, a, s');
+ *                        row_ptr and col are ignored.
+ * val_type is the type of the val array as passed (IG_BF16 = raw bfloat16
+ * bit patterns, uint16).  store is the type P is kept in on the device; it
+ * may be narrower than val_type (conversion rounds to nearest even, through
+ * fp32 for bf16) but not wider.
+ * Validation (when `validate` != 0): 0 <= P <= 1; every row sums to 1 within
+ * 1e-10 (FP64 input) or 2^-7 * max(1, row length)^(1/2) (narrow input), and
+ * gamma * (largest row sum) < 1; costs finite.  Structural checks (sizes,
+ * column range, non-empty rows) are always made. */
+typedef struct {
+  int64_t n;
+  int32_t m;
+  double gamma;            /* discount factor, in (0, 1) */
+  ig_format fmt;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const void* val;
+  ig_dtype val_type;
+  const double* cost;      /* n*m */
+  ig_dtype store;
+  int32_t inputs_on_device;/* 1: row_ptr, col, val, cost are device pointers */
+  int32_t validate;
+} ig_mdp_desc;
+
+/* Solver parameters.  Algorithm 2's inputs are V0 (the V argument), alpha,
+ * K (max_outer) and W (restart). */
+typedef struct {
+  double alpha;        /* forcing term, in (0, 1); Theorem 1 asks for
+                          alpha < (1 - gamma) / (1 + gamma)                   */
+  int32_t restart;     /* GMRES restart length W, 1..IG_MAX_RESTART          */
+  int32_t max_outer;   /* K: outer (policy) iterations                        */
+  int32_t max_inner;   /* cap on Arnoldi steps per policy evaluation          */
+  double tol;          /* outer stop: ||T V - V||_inf <= tol (absolute)       */
+  ig_mode mode;
+  int32_t opi_sweeps;  /* opi_solve: applications of T^pi per outer step      */
+  int32_t forcing;     /* 0: alpha_k = alpha (Algorithm 2); 1: alpha_k =
+                          min(alpha, sqrt(||T V_k - V_k||_inf)) (a forcing
+                          sequence tending to zero, Theorem 1)                 */
+  double eval_rtol;    /* pi_solve: evaluation residual target relative to
+                          ||g^pi||_inf (exact evaluation taken as GMRES to
+                          this level or to stagnation)                        */
+} ig_params;
+
+typedef struct {
+  int32_t outer;          /* outer iterations performed (Bellman passes - 1)  */
+  int32_t inner;          /* Arnoldi steps (P^pi products inside GMRES)       */
+  int32_t restarts;
+  int32_t bellman_passes;
+  int32_t explicit_residuals; /* true-residual evaluations made for the
+                                 stopping test                                */
+  int32_t breakdowns;     /* Arnoldi steps with ||q||_2 == 0                   */
+  int32_t stagnations;    /* inner loops ended by the stagnation guard        */
+  int32_t converged;      /* 1 if the outer stopping test was met             */
+  double res_inf;         /* ||T V - V||_inf at return                        */
+  double cert_bound;      /* res_inf / (1 - gamma) >= ||V - V*||_inf          */
+  double time_ms;         /* device time of the call (HIP events)             */
+  double alg_bytes;       /* algorithmic HBM bytes the call had to move       */
+} ig_stats;
+
+typedef struct ig_mdp_s* ig_mdp_t;
+
+/* Fill `p` with defaults for discount gamma: alpha = (1-gamma)/(2(1+gamma))
+ * (midpoint of Theorem 1's range), restart 30, max_outer 1000,
+ * max_inner 100000, tol 1e-8, FP64 mode, opi_sweeps 20, forcing 0,
+ * eval_rtol 1e-13. */
+void ig_params_default(ig_params* p, double gamma);
+
+/* Copy P and g to the device in the GPU layout (sliced ELL, 64 states per
+ * slice, for CSR input; row-major for dense input) and allocate the solver
+ * buffers the solvers share; the Krylov workspace is allocated on the first
+ * solve and grown when a later call asks for a longer restart or the FP64
+ * basis.  Problem setting: Section 2.  On success *out owns all device
+ * memory until mdp_destroy.  Errors: IG_E_INVALID (malformed description,
+ * see ig_mdp_desc), IG_E_NOMEM, IG_E_DEVICE. */
+ig_status mdp_create(const ig_mdp_desc* desc, void* stream, ig_mdp_t* out);
+
+/* Release the handle and its device memory (synchronises the device).
+ * NULL is ignored. */
+void mdp_destroy(ig_mdp_t mdp);
+
+/* Layout facts of a handle, for byte accounting. */
+typedef struct {
+  int64_t n;
+  int32_t m;
+  int32_t max_width;      /* widest ELL slice (CSR) or n (dense)               */
+  int64_t nnz;            /* stored transition entries                         */
+  int64_t stored_entries; /* nnz plus ELL padding                              */
+  int64_t p_bytes;        /* device bytes of P (values + column indices)       */
+  ig_dtype store;
+  ig_format fmt;
+  double gamma;
+} ig_mdp_info;
+ig_status mdp_get_info(ig_mdp_t mdp, ig_mdp_info* info);
+
+/* One application of the Bellman operator T with greedy policy extraction
+ * (Section 2: T V = min_pi {g^pi + gamma P^pi V}; GreedyPolicy(V)).
+ *   V[n] in, TV[n] out (may be NULL), pi[n] out (int32, may be NULL),
+ *   res_inf out: ||T V - V||_inf as one double (may be NULL).
+ * All four are device pointers.  Ties go to the lowest action index.
+ * Stream-ordered: returns once the work is enqueued. */
+ig_status bellman_apply(ig_mdp_t mdp, const double* V, double* TV, int32_t* pi,
+                        double* res_inf, void* stream);
+
+/* Inexact policy evaluation by restarted GMRES(W) (the inner loop of
+ * Algorithm 2, Section 3.1): starting from x0 = V, solve
+ * (I - gamma P^pi) V = g^pi until
+ *     ||g^pi - (I - gamma P^pi) V||_inf <= alpha * ||g^pi - (I - gamma P^pi) x0||_inf,
+ * or params->max_inner Arnoldi steps, or a restart cycle that lowers the
+ * residual 2-norm by less than a factor 1 - 1e-6 (stagnation).
+ *   pi[n] int32 in (device), V[n] in/out (device).
+ * Returns IG_E_NOCONV (with V = last iterate) if the rule was not met. */
+ig_status policy_eval_gmres(ig_mdp_t mdp, const int32_t* pi, double* V, const ig_params* params,
+                            ig_stats* stats, void* stream);
+
+/* Algorithm 2 (GMRES(W) policy iteration): V[n] in V0 / out V_k, pi[n] out
+ * GreedyPolicy(V_k), for the first k with ||T V_k - V_k||_inf <= params->tol.
+ * IG_E_NOCONV after max_outer outer steps (V, pi = last iterate). */
+ig_status igmres_pi_solve(ig_mdp_t mdp, double* V, int32_t* pi, const ig_params* params,
+                          ig_stats* stats, void* stream);
+
+/* Policy iteration (Section 2.1): pi_0 = GreedyPolicy(V0); evaluation by
+ * GMRES driven to ||residual||_inf <= eval_rtol * ||g^pi||_inf (or
+ * stagnation); improvement keeps the incumbent action unless another is
+ * better by more than 1e-12 * max(1, ||V||_inf); stops when the policy
+ * repeats.  V out = V^pi of the final policy, pi out. */
+ig_status pi_solve(ig_mdp_t mdp, double* V, int32_t* pi, const ig_params* params,
+                   ig_stats* stats, void* stream);
+
+/* Optimistic policy iteration (Section 2.1): per outer step a greedy policy
+ * and params->opi_sweeps applications of T^pi (the first equals T V_k),
+ * until ||T V - V||_inf <= tol. */
+ig_status opi_solve(ig_mdp_t mdp, double* V, int32_t* pi, const ig_params* params,
+                    ig_stats* stats, void* stream);
+
+/* Inexact policy iteration with value iteration as the inner solver
+ * (Algorithm 1 with IterativeLinearSolver = one application of T^pi_k):
+ * sweeps until ||g^pi - J V_{k+1}||_inf <= alpha ||g^pi - J V_k||_inf. */
+ig_status ipi_vi_solve(ig_mdp_t mdp, double* V, int32_t* pi, const ig_params* params,
+                       ig_stats* stats, void* stream);
+
+/* Measurement support (not part of the method): when bit k of `mask` is set,
+ * every launch of kernel class k on this handle is bracketed by HIP events on
+ * the launch stream.  Classes: 0 Bellman pass, 1 P^pi product (J-apply),
+ * 2 Gram-Schmidt orthogonalisation + Givens update, 3 solution update,
+ * 4 explicit residual, 5 value-iteration sweep, 6 other.  mask 0 disables. */
+#define IG_PROFILE_CLASSES 7
+ig_status ig_profile_enable(ig_mdp_t mdp, unsigned mask);
+/* Sum of event-timed milliseconds and launch counts per class since the last
+ * reset (synchronises on the recorded events).  ms and launches have
+ * IG_PROFILE_CLASSES entries (host memory). */
+ig_status ig_profile_read(ig_mdp_t mdp, double* ms, int64_t* launches, int reset);
+
+/* Thread-local description of the last error (never NULL). */
+const char* ig_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGMRES_H */

@@ -1,0 +1,171 @@
+// Internal definitions shared by the HIP sources of libigmres (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/igmres.h"
+
+namespace ig {
+
+// ---------------------------------------------------------------------------
+// storage types
+// ---------------------------------------------------------------------------
+struct bf16 {
+  uint16_t bits;
+};
+
+__device__ __forceinline__ double to_d(double x) { return x; }
+__device__ __forceinline__ double to_d(float x) { return (double)x; }
+__device__ __forceinline__ double to_d(bf16 x) {
+  return (double)__uint_as_float(((uint32_t)x.bits) << 16);
+}
+__device__ __forceinline__ float to_f(double x) { return (float)x; }
+__device__ __forceinline__ float to_f(float x) { return x; }
+__device__ __forceinline__ float to_f(bf16 x) { return __uint_as_float(((uint32_t)x.bits) << 16); }
+
+template <typename T>
+__device__ __forceinline__ T from_d(double x);
+template <>
+__device__ __forceinline__ double from_d<double>(double x) { return x; }
+template <>
+__device__ __forceinline__ float from_d<float>(double x) { return (float)x; }
+
+// ---------------------------------------------------------------------------
+// launch geometry
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;       // CDNA wavefront
+constexpr int kBlock = 256;     // threads per block for every kernel
+constexpr int kSlice = 64;      // states per ELL slice
+constexpr int kMaxBlocks = 2048;   // grid cap of the streaming kernels
+constexpr int kGsBlocks = 512;     // grid cap of the Gram-Schmidt kernels
+constexpr int kMaxW = IG_MAX_RESTART;
+
+// ---------------------------------------------------------------------------
+// sliced ELL views.  Slice b (states 64b .. 64b+63) has width K_b.
+//   full P:     entry (a, j, l) at off[b] + ((a*K_b + j) << 6) + l
+//   compact P^pi entry (j, l) at offp[b] + (j << 6) + l
+// Padding entries have column 0 and value 0.
+// ---------------------------------------------------------------------------
+template <typename VT>
+struct SellP {
+  const int32_t* __restrict__ col;
+  const VT* __restrict__ val;
+  const int64_t* __restrict__ off;   // [nslices]
+  const int32_t* __restrict__ width; // [nslices]
+};
+
+template <typename VT>
+struct SellPi {
+  int32_t* __restrict__ col;
+  VT* __restrict__ val;
+  const int64_t* __restrict__ off;   // [nslices]
+  const int32_t* __restrict__ width; // [nslices]
+};
+
+// ---------------------------------------------------------------------------
+// device-side scalar state of a solve (one per handle)
+// ---------------------------------------------------------------------------
+struct DevStatus {
+  double phi_inf;     // Bellman pass: ||T V - V||_inf
+  double phi_l2sq;    //               ||T V - V||_2^2
+  double res_inf;     // explicit residual ||g - J V||_inf
+  double res_l2sq;    //                   ||g - J V||_2^2
+  double eta;         // last Arnoldi step: ||q||_2 after orthogonalisation
+  double rho;         // |g_hat(i+1)| = residual 2-norm of the LSQ problem
+  double beta;        // 2-norm of the residual that started the cycle
+  double aux;         // kernel-specific scalar (e.g. VI sweep difference)
+  double vmax;        // ||V||_inf seen by the last residual pass
+  int32_t nonfinite;  // NaN/Inf seen in the last Bellman pass
+  int32_t changes;    // policy entries changed by the last improvement
+
+};
+
+struct GivensState {
+  double R[(kMaxW + 1) * kMaxW];  // column-major, leading dim kMaxW+1
+  double cs[kMaxW];
+  double sn[kMaxW];
+  double g[kMaxW + 1];
+  double h[kMaxW + 1];   // current Hessenberg column (first CGS pass, then h1 + h2)
+  double h2[kMaxW + 1];  // second CGS pass coefficients
+};
+
+// Reduction context: per-block partials and a self-resetting ticket.
+struct RedCtx {
+  double* part;        // [gridDim.x * nv]
+  unsigned int* ticket;
+};
+
+// ---------------------------------------------------------------------------
+// wave / block reductions (deterministic: fixed shuffle and LDS order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// op: 0 = sum, 1 = max.  Result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV]) {
+  __shared__ double sh[NV][kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = op[k] ? wave_max(v[k]) : wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double a = sh[k][0];
+      for (int w = 1; w < kBlock / kWave; ++w) a = op[k] ? fmax(a, sh[k][w]) : a + sh[k][w];
+      v[k] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// Write this block's partials; return true in the block that finished last
+// (all threads of that block), after which finish_partials() may read all.
+template <int NV>
+__device__ __forceinline__ bool publish_partials(const double (&v)[NV], RedCtx red) {
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red.part[blockIdx.x * NV + k] = v[k];
+    __threadfence();
+    unsigned t = atomicInc(red.ticket, gridDim.x - 1);  // wraps to 0 for the next launch
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+// In the last block: reduce the nv partials of every block in a fixed order.
+template <int NV>
+__device__ __forceinline__ void finish_partials(double (&v)[NV], const int (&op)[NV], RedCtx red) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;  // every reduced quantity is >= 0
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double x = red.part[b * NV + k];
+      v[k] = op[k] ? fmax(v[k], x) : v[k] + x;
+    }
+  }
+  block_reduce<NV>(v, op);
+}
+
+}  // namespace ig

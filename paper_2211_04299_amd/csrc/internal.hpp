@@ -1,0 +1,135 @@
+// Host-side internals of libigmres: the MDP handle, its workspace and the
+// kernel launchers (one .hip file per kernel family).
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+
+namespace ig {
+
+// Error helper: sets the thread-local message and returns the status.
+ig_status fail(ig_status s, const std::string& msg);
+#define IG_HIP(call)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::ig::fail(IG_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// kernel classes for the optional per-class event timing
+enum KClass { KC_BELLMAN = 0, KC_JAPPLY, KC_GS, KC_UPDATE, KC_RESID, KC_VI, KC_OTHER, KC_COUNT };
+
+struct Workspace {
+  int W = 0;           // restart capacity
+  bool fp32 = false;   // basis type
+  void* Q = nullptr;   // (W+1) x n basis, column j at Q + j*n
+  void* wA = nullptr;  // Arnoldi vectors (ping-pong)
+  void* wB = nullptr;
+  double* Vb = nullptr;   // iterate at the start of the restart cycle
+  double* r = nullptr;    // Phi_k / explicit residual
+  double* t = nullptr;    // spare n-vector (VI ping-pong, evaluation)
+  int32_t* pi = nullptr;  // internal policy buffer
+};
+
+struct Mdp {
+  int device = 0;
+  int64_t n = 0;
+  int m = 0;
+  double gamma = 0;
+  ig_format fmt = IG_FMT_CSR;
+  ig_dtype store = IG_FP64;
+  int vb = 8;  // bytes per stored value
+
+  // sliced ELL (CSR input)
+  int64_t nslices = 0;
+  int maxK = 0;
+  int64_t nnz = 0, stored = 0, stored_pi = 0;
+  int32_t* col = nullptr;
+  void* val = nullptr;
+  int64_t* off = nullptr;
+  int32_t* width = nullptr;
+  int64_t* offp = nullptr;
+  int32_t* pcol = nullptr;  // compact P^pi
+  void* pval = nullptr;
+  std::vector<int32_t> h_width;
+
+  // dense input: P[s][a][s'] row-major
+  void* P = nullptr;
+
+  double* cost = nullptr;  // [m][n] (transposed)
+  double* cpi = nullptr;   // g^pi
+
+  DevStatus* st = nullptr;      // device
+  DevStatus* hst = nullptr;     // pinned host mirror
+  GivensState* gs = nullptr;    // device
+  double* part = nullptr;       // reduction partials
+  unsigned int* ticket = nullptr;
+  Workspace ws;
+
+  // lanes per state of the streaming kernels
+  int G_bell = 1, G_jap = 1;
+  int grid_stream = 1, grid_gs = 1;
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // optional per-class kernel timing
+  unsigned prof_mask = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[KC_COUNT];
+  size_t prof_used[KC_COUNT] = {0};
+  double cost_max = 0;  // max |g(s, a)|
+};
+
+// per-class timing around one launch (no-op unless the class is enabled)
+struct ProfScope {
+  Mdp& d;
+  KClass k;
+  hipStream_t s;
+  hipEvent_t e1 = nullptr;
+  ProfScope(Mdp& d_, KClass k_, hipStream_t s_);
+  ~ProfScope();
+};
+
+RedCtx red_ctx(Mdp& d);
+ig_status ensure_workspace(Mdp& d, int W, bool fp32);
+ig_status sync_status(Mdp& d, hipStream_t s);
+
+// ---- sparse (sliced ELL) launchers --------------------------------------
+// Bellman pass: TV (nullable), Phi = TV - V, pi, g^pi, compact P^pi and the
+// reductions max|Phi|, ||Phi||^2, #nonfinite, #changes into the status.
+// pi_old != nullptr: keep the incumbent unless another action is better by
+// more than tie_abs.
+void launch_bellman_sparse(Mdp& d, const double* V, double* TV, double* Phi, int32_t* pi,
+                           const int32_t* pi_old, double tie_abs, bool compact, hipStream_t s);
+// y = xs - gamma P^pi xs with xs = x * scale, scale = 1/(*eta) (eta == nullptr:
+// scale 1); q_out (nullable) receives xs.  fp32: basis in float.
+void launch_japply_sparse(Mdp& d, bool fp32, const void* x, const double* eta, void* q_out,
+                          void* y, hipStream_t s);
+// r = g^pi - (V - gamma P^pi V) in FP64, with max|r| and ||r||^2 into status.
+void launch_residual_sparse(Mdp& d, const double* V, double* r, hipStream_t s);
+// Vout = g^pi + gamma P^pi Vin (FP64), max|Vout - Vin| into status.aux.
+void launch_vi_sweep_sparse(Mdp& d, const double* Vin, double* Vout, hipStream_t s);
+// compact P^pi and g^pi for a given policy; #invalid entries into status.changes
+void launch_gather_policy_sparse(Mdp& d, const int32_t* pi, hipStream_t s);
+
+// ---- dense launchers (same contracts) ------------------------------------
+void launch_bellman_dense(Mdp& d, const double* V, double* TV, double* Phi, int32_t* pi,
+                          const int32_t* pi_old, double tie_abs, hipStream_t s);
+void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* eta,
+                         void* q_out, void* y, hipStream_t s);
+void launch_residual_dense(Mdp& d, const int32_t* pi, const double* V, double* r, hipStream_t s);
+void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double* Vout,
+                           hipStream_t s);
+void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s);
+
+// ---- Krylov (Gram-Schmidt, Givens, update) -------------------------------
+// Q_0 = r / sqrt(*l2sq); Givens state reset with g_hat = beta e_1.
+void launch_form_q0(Mdp& d, bool fp32, const double* r, const double* l2sq, hipStream_t s);
+// one CGS2 Arnoldi orthogonalisation of w against Q_0..Q_{i-1}, then the
+// Givens update of column i-1; eta and rho into status.
+void launch_arnoldi_orth(Mdp& d, bool fp32, int i, void* w, hipStream_t s);
+// V = Vb + sum_{j<i} y_j Q_j with R y = g_hat (back substitution per block)
+void launch_update(Mdp& d, bool fp32, int i, const double* Vb, double* V, hipStream_t s);
+
+}  // namespace ig

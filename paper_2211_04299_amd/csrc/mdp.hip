@@ -1,0 +1,481 @@
+// MDP handle: validation of the problem data (Section 2 of the paper: finite
+// S and A, row-stochastic P, bounded g, gamma in (0,1)), conversion to the
+// device layouts, workspace and per-class event timing.
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace ig {
+
+thread_local std::string g_last_error = "no error";
+
+ig_status fail(ig_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+RedCtx red_ctx(Mdp& d) { return RedCtx{d.part, d.ticket}; }
+
+ig_status sync_status(Mdp& d, hipStream_t s) {
+  IG_HIP(hipMemcpyAsync(d.hst, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  IG_HIP(hipStreamSynchronize(s));
+  return IG_OK;
+}
+
+ProfScope::ProfScope(Mdp& d_, KClass k_, hipStream_t s_) : d(d_), k(k_), s(s_) {
+  if (!(d.prof_mask & (1u << k))) return;
+  auto& pool = d.prof_ev[k];
+  if (d.prof_used[k] == pool.size()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    pool.emplace_back(a, b);
+  }
+  auto& pr = pool[d.prof_used[k]++];
+  (void)hipEventRecord(pr.first, s);
+  e1 = pr.second;
+}
+ProfScope::~ProfScope() {
+  if (e1) (void)hipEventRecord(e1, s);
+}
+
+namespace {
+
+inline uint16_t f32_to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+inline double bf16_to_f64(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+inline int dtype_bytes(ig_dtype t) { return t == IG_FP64 ? 8 : (t == IG_FP32 ? 4 : 2); }
+
+// value e of the caller's array as a double
+struct ValReader {
+  const void* p;
+  ig_dtype t;
+  double operator()(int64_t e) const {
+    switch (t) {
+      case IG_FP64: return ((const double*)p)[e];
+      case IG_FP32: return (double)((const float*)p)[e];
+      default: return bf16_to_f64(((const uint16_t*)p)[e]);
+    }
+  }
+};
+
+// store x (already representable in the input type) in the storage type,
+// returning the stored value as a double
+inline double store_val(void* dst, int64_t pos, ig_dtype st, double x) {
+  switch (st) {
+    case IG_FP64: ((double*)dst)[pos] = x; return x;
+    case IG_FP32: {
+      const float f = (float)x;
+      ((float*)dst)[pos] = f;
+      return (double)f;
+    }
+    default: {
+      const uint16_t b = f32_to_bf16((float)x);
+      ((uint16_t*)dst)[pos] = b;
+      return bf16_to_f64(b);
+    }
+  }
+}
+
+template <typename T>
+ig_status dmalloc(T** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc((void**)p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(IG_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return IG_OK;
+}
+
+void free_all(Mdp* d) {
+  auto F = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  F(d->col); F(d->val); F(d->off); F(d->width); F(d->offp); F(d->pcol); F(d->pval);
+  F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->ticket);
+  F(d->ws.Q); F(d->ws.wA); F(d->ws.wB); F(d->ws.Vb); F(d->ws.r); F(d->ws.t); F(d->ws.pi);
+  if (d->hst) (void)hipHostFree(d->hst);
+  if (d->ev0) (void)hipEventDestroy(d->ev0);
+  if (d->ev1) (void)hipEventDestroy(d->ev1);
+  for (auto& pool : d->prof_ev)
+    for (auto& pr : pool) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+}
+
+int pow2_at_least(int64_t x, int cap) {
+  int p = 1;
+  while (p < x && p < cap) p <<= 1;
+  return p;
+}
+
+template <typename T>
+std::vector<T> to_host(const T* p, size_t count, bool on_device, ig_status* st) {
+  std::vector<T> v;
+  *st = IG_OK;
+  if (!on_device) return v;
+  v.resize(count);
+  if (count && hipMemcpy(v.data(), p, count * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    *st = fail(IG_E_DEVICE, "copy of device input to host failed");
+  }
+  return v;
+}
+
+}  // namespace
+
+ig_status ensure_workspace(Mdp& d, int W, bool fp32) {
+  Workspace& w = d.ws;
+  const size_t n = (size_t)d.n;
+  if (!w.Vb) {
+    if (dmalloc(&w.Vb, n * 8) || dmalloc(&w.r, n * 8) || dmalloc(&w.t, n * 8) ||
+        dmalloc(&w.pi, n * 4))
+      return IG_E_NOMEM;
+  }
+  if (w.Q && w.W >= W && w.fp32 == fp32) return IG_OK;
+  if (w.Q) (void)hipFree(w.Q);
+  if (w.wA) (void)hipFree(w.wA);
+  if (w.wB) (void)hipFree(w.wB);
+  w.Q = w.wA = w.wB = nullptr;
+  w.W = 0;
+  const size_t xb = fp32 ? 4 : 8;
+  if (dmalloc(&w.Q, (size_t)(W + 1) * n * xb) || dmalloc(&w.wA, n * xb) || dmalloc(&w.wB, n * xb))
+    return IG_E_NOMEM;
+  w.W = W;
+  w.fp32 = fp32;
+  return IG_OK;
+}
+
+static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d) {
+  if (!desc) return fail(IG_E_INVALID, "desc is NULL");
+  const int64_t n = desc->n;
+  const int m = desc->m;
+  if (n < 1 || m < 1) return fail(IG_E_INVALID, "need n >= 1 and m >= 1");
+  if (n > (int64_t)INT32_MAX) return fail(IG_E_INVALID, "n must fit in int32 column indices");
+  if (!(desc->gamma > 0.0 && desc->gamma < 1.0)) return fail(IG_E_INVALID, "gamma must be in (0,1)");
+  if (desc->fmt != IG_FMT_CSR && desc->fmt != IG_FMT_DENSE) return fail(IG_E_INVALID, "bad format");
+  for (ig_dtype t : {desc->val_type, desc->store})
+    if (t != IG_FP64 && t != IG_FP32 && t != IG_BF16) return fail(IG_E_INVALID, "bad dtype");
+  if (dtype_bytes(desc->store) > dtype_bytes(desc->val_type))
+    return fail(IG_E_INVALID, "storage type wider than the input type");
+  if (!desc->val || !desc->cost) return fail(IG_E_INVALID, "val and cost are required");
+  if (desc->fmt == IG_FMT_CSR && (!desc->row_ptr || !desc->col))
+    return fail(IG_E_INVALID, "CSR needs row_ptr and col");
+
+  d->n = n;
+  d->m = m;
+  d->gamma = desc->gamma;
+  d->fmt = desc->fmt;
+  d->store = desc->store;
+  d->vb = dtype_bytes(desc->store);
+  const int64_t R = n * (int64_t)m;
+  const bool ondev = desc->inputs_on_device != 0;
+  ig_status st;
+
+  // ---- costs (always checked finite) ----
+  std::vector<double> cost_h = to_host(desc->cost, (size_t)R, ondev, &st);
+  if (st) return st;
+  const double* cost = ondev ? cost_h.data() : desc->cost;
+  std::vector<double> cost_t((size_t)R);
+  int bad_cost = 0;
+  double cmax = 0.0;
+#pragma omp parallel for reduction(+ : bad_cost) reduction(max : cmax)
+  for (int64_t s = 0; s < n; ++s)
+    for (int a = 0; a < m; ++a) {
+      const double c = cost[s * m + a];
+      if (!std::isfinite(c)) ++bad_cost;
+      else cmax = std::max(cmax, std::fabs(c));
+      cost_t[(size_t)a * n + s] = c;
+    }
+  if (bad_cost) return fail(IG_E_INVALID, "costs must be finite");
+  d->cost_max = cmax;
+
+  const double sum_tol = desc->val_type == IG_FP64 ? 1e-10 : 1.0 / 64.0;
+  const bool validate = desc->validate != 0;
+
+  if (desc->fmt == IG_FMT_CSR) {
+    std::vector<int64_t> rp_h = to_host(desc->row_ptr, (size_t)R + 1, ondev, &st);
+    if (st) return st;
+    const int64_t* rp = ondev ? rp_h.data() : desc->row_ptr;
+    if (rp[0] != 0) return fail(IG_E_INVALID, "row_ptr[0] must be 0");
+    int bad_rows = 0;
+#pragma omp parallel for reduction(+ : bad_rows)
+    for (int64_t r = 0; r < R; ++r)
+      if (rp[r + 1] <= rp[r]) ++bad_rows;
+    if (bad_rows) return fail(IG_E_INVALID, "every (s,a) row must be non-empty and row_ptr increasing");
+    const int64_t nnz = rp[R];
+    std::vector<int32_t> col_h = to_host(desc->col, (size_t)nnz, ondev, &st);
+    if (st) return st;
+    const int32_t* col = ondev ? col_h.data() : desc->col;
+    std::vector<uint8_t> val_h;
+    const void* valp = desc->val;
+    if (ondev) {
+      val_h.resize((size_t)nnz * dtype_bytes(desc->val_type));
+      if (hipMemcpy(val_h.data(), desc->val, val_h.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(IG_E_DEVICE, "copy of device values failed");
+      valp = val_h.data();
+    }
+    const ValReader rv{valp, desc->val_type};
+
+    // widths per 64-state slice
+    const int64_t ns = (n + kSlice - 1) / kSlice;
+    std::vector<int32_t> width((size_t)ns, 0);
+    int64_t maxlen = 0;
+#pragma omp parallel for reduction(max : maxlen)
+    for (int64_t b = 0; b < ns; ++b) {
+      int64_t w = 0;
+      for (int64_t s = b * kSlice; s < std::min(n, (b + 1) * kSlice); ++s)
+        for (int a = 0; a < m; ++a) w = std::max(w, rp[s * m + a + 1] - rp[s * m + a]);
+      width[b] = (int32_t)w;
+      maxlen = std::max(maxlen, w);
+    }
+    if (maxlen > n) return fail(IG_E_INVALID, "a row has more entries than states");
+    std::vector<int64_t> off((size_t)ns), offp((size_t)ns);
+    int64_t tot = 0, totp = 0;
+    for (int64_t b = 0; b < ns; ++b) {
+      off[b] = tot;
+      offp[b] = totp;
+      tot += (int64_t)m * width[b] * kSlice;
+      totp += (int64_t)width[b] * kSlice;
+    }
+    std::vector<int32_t> scol((size_t)tot, 0);
+    std::vector<uint8_t> sval((size_t)tot * d->vb, 0);
+    int bad_col = 0, bad_dup = 0, bad_p = 0, bad_sum = 0;
+    double max_stored_sum = 0.0;
+#pragma omp parallel reduction(+ : bad_col, bad_dup, bad_p, bad_sum) reduction(max : max_stored_sum)
+    {
+      std::vector<int32_t> tmp;
+#pragma omp for schedule(dynamic, 16)
+      for (int64_t b = 0; b < ns; ++b) {
+        const int Kb = width[b];
+        for (int64_t s = b * kSlice; s < std::min(n, (b + 1) * kSlice); ++s) {
+          const int l = (int)(s & (kSlice - 1));
+          for (int a = 0; a < m; ++a) {
+            const int64_t r = s * m + a, lo = rp[r], hi = rp[r + 1];
+            double sum = 0.0, ssum = 0.0;
+            tmp.assign(col + lo, col + hi);
+            for (int64_t e = lo; e < hi; ++e) {
+              const int32_t c = col[e];
+              if (c < 0 || c >= n) ++bad_col;
+              const double p = rv(e);
+              if (validate && !(p >= 0.0 && p <= 1.0)) ++bad_p;
+              sum += p;
+              const int64_t pos = off[b] + (((int64_t)a * Kb + (e - lo)) << 6) + l;
+              scol[pos] = (c >= 0 && c < n) ? c : 0;
+              ssum += store_val(sval.data(), pos, d->store, p);
+            }
+            std::sort(tmp.begin(), tmp.end());
+            for (size_t k = 1; k < tmp.size(); ++k)
+              if (tmp[k] == tmp[k - 1]) ++bad_dup;
+            if (validate && !(std::fabs(sum - 1.0) <= sum_tol)) ++bad_sum;
+            max_stored_sum = std::max(max_stored_sum, ssum);
+          }
+        }
+      }
+    }
+    if (bad_col) return fail(IG_E_INVALID, "column index out of range");
+    if (bad_dup) return fail(IG_E_INVALID, "repeated column inside a row");
+    if (bad_p) return fail(IG_E_INVALID, "probabilities must lie in [0,1]");
+    if (bad_sum) return fail(IG_E_INVALID, "a transition row does not sum to 1");
+    if (validate && !(d->gamma * max_stored_sum < 1.0))
+      return fail(IG_E_INVALID, "gamma * (largest stored row sum) must be < 1");
+
+    d->nslices = ns;
+    d->maxK = (int)maxlen;
+    d->nnz = nnz;
+    d->stored = tot;
+    d->stored_pi = totp;
+    d->h_width = width;
+    if (dmalloc(&d->col, (size_t)tot * 4) || dmalloc(&d->val, (size_t)tot * d->vb) ||
+        dmalloc(&d->off, (size_t)ns * 8) || dmalloc(&d->offp, (size_t)ns * 8) ||
+        dmalloc(&d->width, (size_t)ns * 4) || dmalloc(&d->pcol, (size_t)totp * 4) ||
+        dmalloc(&d->pval, (size_t)totp * d->vb))
+      return IG_E_NOMEM;
+    IG_HIP(hipMemcpy(d->col, scol.data(), (size_t)tot * 4, hipMemcpyHostToDevice));
+    IG_HIP(hipMemcpy(d->val, sval.data(), (size_t)tot * d->vb, hipMemcpyHostToDevice));
+    IG_HIP(hipMemcpy(d->off, off.data(), (size_t)ns * 8, hipMemcpyHostToDevice));
+    IG_HIP(hipMemcpy(d->offp, offp.data(), (size_t)ns * 8, hipMemcpyHostToDevice));
+    IG_HIP(hipMemcpy(d->width, width.data(), (size_t)ns * 4, hipMemcpyHostToDevice));
+    IG_HIP(hipMemset(d->pcol, 0, (size_t)totp * 4));
+    IG_HIP(hipMemset(d->pval, 0, (size_t)totp * d->vb));
+
+    // lanes per state: enough lanes in flight to cover latency on 256 CUs
+    const int64_t target = (int64_t)1 << 18;
+    const int want = pow2_at_least((target + n - 1) / n, 64);
+    d->G_bell = std::min(pow2_at_least(m, 64), want);
+    d->G_jap = std::min(pow2_at_least(std::max<int64_t>(1, maxlen), 64), want);
+  } else {
+    const int64_t total = R * n;
+    std::vector<uint8_t> val_h;
+    const void* valp = desc->val;
+    if (ondev) {
+      val_h.resize((size_t)total * dtype_bytes(desc->val_type));
+      if (hipMemcpy(val_h.data(), desc->val, val_h.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(IG_E_DEVICE, "copy of device values failed");
+      valp = val_h.data();
+    }
+    const ValReader rv{valp, desc->val_type};
+    std::vector<uint8_t> sval((size_t)total * d->vb);
+    int bad_p = 0, bad_sum = 0;
+    double max_stored_sum = 0.0;
+#pragma omp parallel for reduction(+ : bad_p, bad_sum) reduction(max : max_stored_sum) schedule(dynamic, 64)
+    for (int64_t r = 0; r < R; ++r) {
+      double sum = 0.0, ssum = 0.0;
+      for (int64_t e = r * n; e < (r + 1) * n; ++e) {
+        const double p = rv(e);
+        if (validate && !(p >= 0.0 && p <= 1.0)) ++bad_p;
+        sum += p;
+        ssum += store_val(sval.data(), e, d->store, p);
+      }
+      if (validate && !(std::fabs(sum - 1.0) <= sum_tol)) ++bad_sum;
+      max_stored_sum = std::max(max_stored_sum, ssum);
+    }
+    if (bad_p) return fail(IG_E_INVALID, "probabilities must lie in [0,1]");
+    if (bad_sum) return fail(IG_E_INVALID, "a transition row does not sum to 1");
+    if (validate && !(d->gamma * max_stored_sum < 1.0))
+      return fail(IG_E_INVALID, "gamma * (largest stored row sum) must be < 1");
+    d->nnz = total;
+    d->stored = total;
+    d->maxK = (int)n;
+    if (dmalloc(&d->P, (size_t)total * d->vb)) return IG_E_NOMEM;
+    IG_HIP(hipMemcpy(d->P, sval.data(), (size_t)total * d->vb, hipMemcpyHostToDevice));
+  }
+
+  if (dmalloc(&d->cost, (size_t)R * 8) || dmalloc(&d->cpi, (size_t)n * 8) ||
+      dmalloc(&d->st, sizeof(DevStatus)) || dmalloc(&d->gs, sizeof(GivensState)) ||
+      dmalloc(&d->part, (size_t)kGsBlocks * (kMaxW + 1) * 8 + (size_t)kMaxBlocks * 8 * 8) ||
+      dmalloc(&d->ticket, 64))
+    return IG_E_NOMEM;
+  IG_HIP(hipMemcpy(d->cost, cost_t.data(), (size_t)R * 8, hipMemcpyHostToDevice));
+  IG_HIP(hipMemset(d->st, 0, sizeof(DevStatus)));
+  IG_HIP(hipMemset(d->gs, 0, sizeof(GivensState)));
+  IG_HIP(hipMemset(d->ticket, 0, 64));
+  if (hipHostMalloc((void**)&d->hst, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
+    return fail(IG_E_NOMEM, "hipHostMalloc failed");
+  std::memset(d->hst, 0, sizeof(DevStatus));
+  IG_HIP(hipEventCreate(&d->ev0));
+  IG_HIP(hipEventCreate(&d->ev1));
+  IG_HIP(hipGetDevice(&d->device));
+  IG_HIP(hipDeviceSynchronize());
+  (void)stream;
+  return IG_OK;
+}
+
+}  // namespace ig
+
+struct ig_mdp_s {
+  ig::Mdp d;
+};
+
+extern "C" {
+
+const char* ig_last_error(void) { return ig::g_last_error.c_str(); }
+
+void ig_params_default(ig_params* p, double gamma) {
+  if (!p) return;
+  p->alpha = 0.5 * (1.0 - gamma) / (1.0 + gamma);
+  p->restart = 30;
+  p->max_outer = 1000;
+  p->max_inner = 100000;
+  p->tol = 1e-8;
+  p->mode = IG_MODE_FP64;
+  p->opi_sweeps = 20;
+  p->forcing = 0;
+  p->eval_rtol = 1e-13;
+}
+
+ig_status mdp_create(const ig_mdp_desc* desc, void* stream, ig_mdp_t* out) {
+  if (!out) return ig::fail(IG_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<ig_mdp_s> h;
+  try {
+    h.reset(new ig_mdp_s());
+  } catch (...) {
+    return ig::fail(IG_E_NOMEM, "host allocation failed");
+  }
+  ig_status st;
+  try {
+    st = ig::create_impl(desc, (hipStream_t)stream, &h->d);
+  } catch (const std::bad_alloc&) {
+    st = ig::fail(IG_E_NOMEM, "host allocation failed while converting the MDP");
+  } catch (...) {
+    st = ig::fail(IG_E_INVALID, "unexpected failure while converting the MDP");
+  }
+  if (st != IG_OK) {
+    ig::free_all(&h->d);
+    return st;
+  }
+  *out = h.release();
+  return IG_OK;
+}
+
+void mdp_destroy(ig_mdp_t mdp) {
+  if (!mdp) return;
+  (void)hipDeviceSynchronize();
+  ig::free_all(&mdp->d);
+  delete mdp;
+}
+
+ig_status mdp_get_info(ig_mdp_t mdp, ig_mdp_info* info) {
+  if (!mdp || !info) return ig::fail(IG_E_INVALID, "NULL argument");
+  const ig::Mdp& d = mdp->d;
+  info->n = d.n;
+  info->m = d.m;
+  info->max_width = d.maxK;
+  info->nnz = d.nnz;
+  info->stored_entries = d.stored;
+  info->p_bytes = d.stored * (int64_t)(d.vb + (d.fmt == IG_FMT_CSR ? 4 : 0));
+  info->store = d.store;
+  info->fmt = d.fmt;
+  info->gamma = d.gamma;
+  return IG_OK;
+}
+
+ig_status ig_profile_enable(ig_mdp_t mdp, unsigned mask) {
+  if (!mdp) return ig::fail(IG_E_INVALID, "NULL handle");
+  mdp->d.prof_mask = mask;
+  return IG_OK;
+}
+
+ig_status ig_profile_read(ig_mdp_t mdp, double* ms, int64_t* launches, int reset) {
+  if (!mdp || !ms || !launches) return ig::fail(IG_E_INVALID, "NULL argument");
+  ig::Mdp& d = mdp->d;
+  for (int k = 0; k < ig::KC_COUNT; ++k) {
+    double tot = 0.0;
+    for (size_t i = 0; i < d.prof_used[k]; ++i) {
+      auto& pr = d.prof_ev[k][i];
+      if (hipEventSynchronize(pr.second) != hipSuccess) return ig::fail(IG_E_DEVICE, "event sync");
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess)
+        return ig::fail(IG_E_DEVICE, "event elapsed");
+      tot += t;
+    }
+    ms[k] = tot;
+    launches[k] = (int64_t)d.prof_used[k];
+    if (reset) d.prof_used[k] = 0;
+  }
+  return IG_OK;
+}
+
+}  // extern "C"
+
+// access for the solver translation unit
+namespace ig {
+Mdp* handle_of(ig_mdp_t h) { return h ? &h->d : nullptr; }
+}  // namespace ig

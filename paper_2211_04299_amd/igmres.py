@@ -1,0 +1,237 @@
+"""Thin ctypes binding of libigmres.so (C-ABI in include/igmres.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies device memory and the current HIP stream.  Importing this
+module loads the library and raises ImportError if it has not been built --
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libigmres.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2211_04299_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+# ---- enums (include/igmres.h) ---------------------------------------------
+IG_OK, IG_E_INVALID, IG_E_NOMEM, IG_E_DEVICE, IG_E_NOCONV, IG_E_NUMERIC, IG_E_TOO_LARGE = (
+    0, -1, -2, -3, -4, -5, -6)
+STATUS_NAMES = {0: "IG_OK", -1: "IG_E_INVALID", -2: "IG_E_NOMEM", -3: "IG_E_DEVICE",
+                -4: "IG_E_NOCONV", -5: "IG_E_NUMERIC", -6: "IG_E_TOO_LARGE"}
+IG_FMT_CSR, IG_FMT_DENSE = 0, 1
+IG_FP64, IG_FP32, IG_BF16 = 0, 1, 2
+DTYPES = {"fp64": IG_FP64, "fp32": IG_FP32, "bf16": IG_BF16}
+IG_MODE_FP64, IG_MODE_MIXED = 0, 1
+IG_MAX_RESTART = 128
+IG_PROFILE_CLASSES = 7
+PROFILE_CLASS_NAMES = ["bellman", "japply", "gram_schmidt", "update", "residual", "vi_sweep", "other"]
+
+EXPORTS = ["ig_params_default", "mdp_create", "mdp_destroy", "mdp_get_info", "bellman_apply",
+           "policy_eval_gmres", "igmres_pi_solve", "pi_solve", "opi_solve", "ipi_vi_solve",
+           "ig_profile_enable", "ig_profile_read", "ig_last_error"]
+
+
+class MdpDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("gamma", C.c_double), ("fmt", C.c_int),
+                ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("val_type", C.c_int), ("cost", C.c_void_p), ("store", C.c_int),
+                ("inputs_on_device", C.c_int32), ("validate", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("restart", C.c_int32), ("max_outer", C.c_int32),
+                ("max_inner", C.c_int32), ("tol", C.c_double), ("mode", C.c_int),
+                ("opi_sweeps", C.c_int32), ("forcing", C.c_int32), ("eval_rtol", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("outer", C.c_int32), ("inner", C.c_int32), ("restarts", C.c_int32),
+                ("bellman_passes", C.c_int32), ("explicit_residuals", C.c_int32),
+                ("breakdowns", C.c_int32), ("stagnations", C.c_int32), ("converged", C.c_int32),
+                ("res_inf", C.c_double), ("cert_bound", C.c_double), ("time_ms", C.c_double),
+                ("alg_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MdpInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("max_width", C.c_int32), ("nnz", C.c_int64),
+                ("stored_entries", C.c_int64), ("p_bytes", C.c_int64), ("store", C.c_int),
+                ("fmt", C.c_int), ("gamma", C.c_double)]
+
+
+_P = C.c_void_p
+_sig = {
+    "ig_params_default": (None, [C.POINTER(Params), C.c_double]),
+    "mdp_create": (C.c_int, [C.POINTER(MdpDesc), _P, C.POINTER(_P)]),
+    "mdp_destroy": (None, [_P]),
+    "mdp_get_info": (C.c_int, [_P, C.POINTER(MdpInfo)]),
+    "bellman_apply": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "policy_eval_gmres": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
+    "igmres_pi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
+    "pi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
+    "opi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
+    "ipi_vi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
+    "ig_profile_enable": (C.c_int, [_P, C.c_uint]),
+    "ig_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
+    "ig_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class IgError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.ig_last_error().decode()
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def _check(status, where, ok=(IG_OK,)):
+    if status not in ok:
+        raise IgError(status, where)
+    return status
+
+
+def last_error() -> str:
+    return _lib.ig_last_error().decode()
+
+
+def params_default(gamma: float, **kw) -> Params:
+    p = Params()
+    _lib.ig_params_default(C.byref(p), float(gamma))
+    for k, v in kw.items():
+        if k == "mode" and isinstance(v, str):
+            v = IG_MODE_MIXED if v == "mixed" else IG_MODE_FP64
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()  # torch tensor
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Mdp:
+    """Owns one device-resident MDP (an ig_mdp_t)."""
+
+    def __init__(self, handle, n, m, gamma):
+        self.handle = handle
+        self.n, self.m, self.gamma = n, m, gamma
+
+    def close(self):
+        if self.handle:
+            _lib.mdp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self) -> MdpInfo:
+        inf = MdpInfo()
+        _check(_lib.mdp_get_info(self.handle, C.byref(inf)), "mdp_get_info")
+        return inf
+
+    # ---- entry points -----------------------------------------------------
+    def bellman_apply(self, V, TV=None, pi=None, res_inf=None, stream=None):
+        _check(_lib.bellman_apply(self.handle, _ptr(V), _ptr(TV), _ptr(pi), _ptr(res_inf),
+                                  _stream(stream)), "bellman_apply")
+
+    def _solve(self, fn, name, V, pi, params, stream, allow_noconv):
+        st = Stats()
+        rc = fn(self.handle, _ptr(V), _ptr(pi), C.byref(params), C.byref(st), _stream(stream))
+        _check(rc, name, (IG_OK, IG_E_NOCONV) if allow_noconv else (IG_OK,))
+        d = st.as_dict()
+        d["status"] = rc
+        return d
+
+    def policy_eval_gmres(self, pi, V, params, stream=None, allow_noconv=False):
+        st = Stats()
+        rc = _lib.policy_eval_gmres(self.handle, _ptr(pi), _ptr(V), C.byref(params), C.byref(st),
+                                    _stream(stream))
+        _check(rc, "policy_eval_gmres", (IG_OK, IG_E_NOCONV) if allow_noconv else (IG_OK,))
+        d = st.as_dict()
+        d["status"] = rc
+        return d
+
+    def igmres_pi_solve(self, V, pi, params, stream=None, allow_noconv=False):
+        return self._solve(_lib.igmres_pi_solve, "igmres_pi_solve", V, pi, params, stream, allow_noconv)
+
+    def pi_solve(self, V, pi, params, stream=None, allow_noconv=False):
+        return self._solve(_lib.pi_solve, "pi_solve", V, pi, params, stream, allow_noconv)
+
+    def opi_solve(self, V, pi, params, stream=None, allow_noconv=False):
+        return self._solve(_lib.opi_solve, "opi_solve", V, pi, params, stream, allow_noconv)
+
+    def ipi_vi_solve(self, V, pi, params, stream=None, allow_noconv=False):
+        return self._solve(_lib.ipi_vi_solve, "ipi_vi_solve", V, pi, params, stream, allow_noconv)
+
+    # ---- measurement ------------------------------------------------------
+    def profile_enable(self, mask: int):
+        _check(_lib.ig_profile_enable(self.handle, mask), "ig_profile_enable")
+
+    def profile_read(self, reset=True):
+        ms = (C.c_double * IG_PROFILE_CLASSES)()
+        cnt = (C.c_int64 * IG_PROFILE_CLASSES)()
+        _check(_lib.ig_profile_read(self.handle, ms, cnt, int(reset)), "ig_profile_read")
+        return {PROFILE_CLASS_NAMES[k]: (ms[k], cnt[k]) for k in range(IG_PROFILE_CLASSES)}
+
+
+def mdp_create(mdp, store: str = "fp64", validate: bool = True, stream=None) -> Mdp:
+    """Create a device MDP from a synth.MDP-like object with host arrays
+    (fmt "csr": row_ptr/col/val; "dense": P).  `mdp.val` / `mdp.P` may be
+    float64, float32 or uint16 (bf16 bit patterns)."""
+    d = MdpDesc()
+    d.n, d.m, d.gamma = mdp.n, mdp.m, float(mdp.gamma)
+    keep = []
+    if mdp.fmt == "csr":
+        d.fmt = IG_FMT_CSR
+        rp = np.ascontiguousarray(mdp.row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(mdp.col, dtype=np.int32)
+        val = np.ascontiguousarray(mdp.val)
+        keep += [rp, col, val]
+        d.row_ptr, d.col, d.val = rp.ctypes.data, col.ctypes.data, val.ctypes.data
+    else:
+        d.fmt = IG_FMT_DENSE
+        val = np.ascontiguousarray(mdp.P)
+        keep.append(val)
+        d.val = val.ctypes.data
+    d.val_type = {np.dtype(np.float64): IG_FP64, np.dtype(np.float32): IG_FP32,
+                  np.dtype(np.uint16): IG_BF16}[val.dtype]
+    cost = np.ascontiguousarray(mdp.cost, dtype=np.float64)
+    keep.append(cost)
+    d.cost = cost.ctypes.data
+    d.store = DTYPES[store]
+    d.inputs_on_device = 0
+    d.validate = int(validate)
+    h = C.c_void_p()
+    _check(_lib.mdp_create(C.byref(d), stream, C.byref(h)), "mdp_create")
+    return Mdp(h, mdp.n, mdp.m, float(mdp.gamma))

@@ -1,0 +1,161 @@
+"""igmres_pi_solve, pi_solve, opi_solve and ipi_vi_solve against V* and pi*
+of the FP64 oracle (PI with dense LU evaluation, pinned by brute force and
+closed forms), plus iteration counts of the literal Algorithm 2."""
+import numpy as np
+import pytest
+
+from oracle import mdp_oracle as O
+from paper_2211_04299_amd import synth
+
+from gpu_helpers import assert_policy_match, dev_vec, host, rel_err, tol_par, zeros
+
+pytestmark = pytest.mark.gpu
+
+
+def igm():
+    from paper_2211_04299_amd import igmres
+    return igmres
+
+
+_cache = {}
+
+
+def reference(name, seed):
+    key = (name, seed)
+    if key not in _cache:
+        mdp = synth.config(name, seed)
+        Vs, pis, _ = O.policy_iteration(mdp)
+        _cache[key] = (mdp, Vs, pis)
+    return _cache[key]
+
+
+def solve(mdp, method="igmres_pi_solve", store="fp64", V0=None, allow_noconv=False, **kw):
+    I = igm()
+    with I.mdp_create(mdp, store=store) as h:
+        V = dev_vec(np.zeros(mdp.n) if V0 is None else V0)
+        pi = zeros(mdp.n, "int32")
+        p = I.params_default(mdp.gamma, **kw)
+        st = getattr(h, method)(V, pi, p, allow_noconv=allow_noconv)
+        return host(V), host(pi), st
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_igmres_c1_parity(seed):
+    mdp, Vs, pis = reference("c1", seed)
+    tol = tol_par(mdp, np.max(np.abs(Vs)))
+    V, pi, st = solve(mdp, tol=tol, restart=20)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+    assert np.max(np.abs(V - Vs)) <= st["cert_bound"] * (1 + 1e-9) + 1e-15
+    # same trajectory as the literal Algorithm 2
+    Vo, pio, sto = O.igmres_pi(mdp, W=20, tol=tol)
+    assert st["outer"] == sto.outer
+    assert abs(st["inner"] - sto.inner) <= sto.outer
+
+
+def test_igmres_c2_bench_configuration():
+    """The timed workload: n=1e4, m=8, k=20, gamma=0.99, W=30, tol 1e-8."""
+    mdp, Vs, pis = reference("c2", 0)
+    V, pi, st = solve(mdp, tol=1e-8, restart=30)
+    assert st["converged"] == 1 and st["res_inf"] <= 1e-8
+    assert rel_err(V, Vs) <= 1e-8
+    Vo, pio, sto = O.igmres_pi(mdp, W=30, tol=1e-8)
+    assert st["outer"] == sto.outer
+    assert abs(st["inner"] - sto.inner) <= sto.outer
+
+
+def test_igmres_c2_parity_tight():
+    mdp, Vs, pis = reference("c2", 0)
+    V, pi, st = solve(mdp, tol=tol_par(mdp, np.max(np.abs(Vs))), restart=30)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+
+
+def test_pi_solve_c2():
+    mdp, Vs, pis = reference("c2", 0)
+    V, pi, st = solve(mdp, method="pi_solve", restart=30)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-10
+    assert_policy_match(mdp, Vs, pis, pi)
+
+
+def test_opi_c2_and_c1():
+    for name in ("c1", "c2"):
+        mdp, Vs, pis = reference(name, 0)
+        V, pi, st = solve(mdp, method="opi_solve", opi_sweeps=20, tol=1e-8)
+        assert st["converged"] == 1
+        assert np.max(np.abs(V - Vs)) <= 1e-8 / (1 - mdp.gamma) * (1 + 1e-6)
+        Vo, _, outer, total = O.opi(mdp, 20, tol=1e-8)
+        assert st["outer"] == outer
+        np.testing.assert_allclose(V, Vo, rtol=1e-10)
+
+
+def test_ipi_vi_c1():
+    mdp, Vs, pis = reference("c1", 1)
+    V, pi, st = solve(mdp, method="ipi_vi_solve", tol=1e-10)
+    assert st["converged"] == 1
+    assert np.max(np.abs(V - Vs)) <= 1e-10 / (1 - mdp.gamma) * (1 + 1e-6)
+
+
+def test_dense_fp64_igmres():
+    mdp = synth.dense_exp(400, 4, 0.99, seed=3)
+    Vs, pis, _ = O.policy_iteration(mdp)
+    V, pi, st = solve(mdp, tol=tol_par(mdp, np.max(np.abs(Vs))), restart=30)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+
+
+@pytest.mark.parametrize("store", ["fp32", "bf16"])
+def test_mixed_precision_against_stored_mdp_oracle(store):
+    mdp = synth.config("c2", seed=1, n=3000)
+    stored = mdp.with_values(val=synth.upcast_values(synth.round_values(mdp.val, store), store))
+    Vs, pis, _ = O.policy_iteration(stored)
+    V, pi, st = solve(mdp, store=store, mode="mixed", restart=30,
+                      tol=tol_par(stored, np.max(np.abs(Vs))))
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-6
+    assert_policy_match(stored, Vs, pis, pi)
+
+
+def test_dense_bf16_mixed():
+    mdp = synth.dense_exp(300, 4, 0.99, seed=5)
+    stored = mdp.with_values(P=synth.upcast_values(synth.round_values(mdp.P, "bf16"), "bf16"))
+    Vs, pis, _ = O.policy_iteration(stored)
+    V, pi, st = solve(mdp, store="bf16", mode="mixed", tol=tol_par(stored, np.max(np.abs(Vs))))
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-6
+
+
+def test_warm_start_at_solution_does_no_inner_work():
+    mdp, Vs, pis = reference("c1", 0)
+    V, pi, st = solve(mdp, V0=Vs, tol=1e-8)
+    assert st["outer"] == 0 and st["inner"] == 0 and st["converged"] == 1
+
+
+def test_single_state_closed_form():
+    mdp = synth.self_loops(1, 3, 0.9, seed=2)
+    V, pi, st = solve(mdp, tol=1e-12)
+    assert V[0] == pytest.approx(mdp.cost.min() / 0.1, rel=1e-12)
+    assert pi[0] == int(np.argmin(mdp.cost))
+
+
+def test_deterministic_bits():
+    mdp, _, _ = reference("c1", 2)
+    a = solve(mdp, tol=1e-10)[0]
+    b = solve(mdp, tol=1e-10)[0]
+    assert np.array_equal(a, b)
+
+
+def test_noconv_and_bad_params():
+    I = igm()
+    mdp, _, _ = reference("c1", 0)
+    V, pi, st = solve(mdp, max_outer=1, tol=1e-14, allow_noconv=True)
+    assert st["status"] == I.IG_E_NOCONV and st["converged"] == 0
+    for kw, code in [(dict(alpha=0.0), I.IG_E_INVALID), (dict(restart=0), I.IG_E_INVALID),
+                     (dict(restart=129), I.IG_E_TOO_LARGE), (dict(tol=0.0), I.IG_E_INVALID)]:
+        with pytest.raises(I.IgError) as e:
+            solve(mdp, **kw)
+        assert e.value.status == code

@@ -1,0 +1,80 @@
+"""mdp_create rejects malformed problem data (Section 2: gamma in (0,1),
+row-stochastic rows, finite costs, column indices in range) on the host,
+before any device work; entry points reject bad parameters."""
+import numpy as np
+import pytest
+
+from paper_2211_04299_amd import synth
+
+
+def igm():
+    from paper_2211_04299_amd import igmres
+    return igmres
+
+
+def base():
+    return synth.sparse_uniform(10, 2, 3, 0.9, seed=0)
+
+
+def expect_invalid(mdp, **kw):
+    I = igm()
+    with pytest.raises(I.IgError) as e:
+        I.mdp_create(mdp, **kw)
+    assert e.value.status == I.IG_E_INVALID, str(e.value)
+    return str(e.value)
+
+
+def test_bad_gamma():
+    for g in (0.0, 1.0, -0.5, 1.5, float("nan")):
+        m = base()
+        m.gamma = g
+        assert "gamma" in expect_invalid(m)
+
+
+def test_row_not_stochastic():
+    m = base()
+    m.val = m.val.copy()
+    m.val[0] += 0.01
+    assert "sum" in expect_invalid(m)
+
+
+def test_negative_probability():
+    m = base()
+    m.val = m.val.copy()
+    m.val[0], m.val[1] = -0.1, m.val[1] + m.val[0] + 0.1
+    assert "[0,1]" in expect_invalid(m)
+
+
+def test_column_out_of_range():
+    m = base()
+    m.col = m.col.copy()
+    m.col[5] = 10
+    assert "range" in expect_invalid(m)
+
+
+def test_repeated_column():
+    m = base()
+    m.col = m.col.copy()
+    m.col[1] = m.col[0]
+    assert "repeated" in expect_invalid(m)
+
+
+def test_empty_row():
+    m = base()
+    rp = m.row_ptr.copy()
+    rp[1] = rp[0]
+    m.row_ptr = rp
+    assert "non-empty" in expect_invalid(m)
+
+
+def test_nonfinite_cost():
+    m = base()
+    m.cost = m.cost.copy()
+    m.cost[3] = np.inf
+    assert "finite" in expect_invalid(m)
+
+
+def test_storage_wider_than_input():
+    m = base()
+    m.val = synth.round_values(m.val, "fp32")
+    assert "wider" in expect_invalid(m, store="fp64")
