@@ -102,8 +102,13 @@ typedef struct {
                           min(alpha, sqrt(||T V_k - V_k||_inf)) (a forcing
                           sequence tending to zero, Theorem 1)                 */
   double eval_rtol;    /* pi_solve: evaluation residual target relative to
-                          ||g^pi||_inf (exact evaluation taken as GMRES to
+                          max |g(s,a)| (exact evaluation taken as GMRES to
                           this level or to stagnation)                        */
+  int32_t engine;      /* igmres_pi_solve: 0 auto, 1 one kernel launch per
+                          step (any size, dense or sparse), 2 a single
+                          persistent launch for the whole solve (sparse,
+                          up to 256*32 slices of 64 states); auto picks 2
+                          when it applies                                     */
 } ig_params;
 
 typedef struct {
@@ -127,7 +132,7 @@ typedef struct ig_mdp_s* ig_mdp_t;
 /* Fill `p` with defaults for discount gamma: alpha = (1-gamma)/(2(1+gamma))
  * (midpoint of Theorem 1's range), restart 30, max_outer 1000,
  * max_inner 100000, tol 1e-8, FP64 mode, opi_sweeps 20, forcing 0,
- * eval_rtol 1e-13. */
+ * eval_rtol 1e-13, engine 0. */
 void ig_params_default(ig_params* p, double gamma);
 
 /* Copy P and g to the device in the GPU layout (sliced ELL, 64 states per
@@ -154,6 +159,9 @@ typedef struct {
   ig_dtype store;
   ig_format fmt;
   double gamma;
+  int32_t persistent_ok;  /* igmres_pi_solve with engine 0 uses one persistent
+                             launch per solve on this handle                */
+  int32_t persistent_blocks;
 } ig_mdp_info;
 ig_status mdp_get_info(ig_mdp_t mdp, ig_mdp_info* info);
 
@@ -207,8 +215,9 @@ ig_status ipi_vi_solve(ig_mdp_t mdp, double* V, int32_t* pi, const ig_params* pa
  * every launch of kernel class k on this handle is bracketed by HIP events on
  * the launch stream.  Classes: 0 Bellman pass, 1 P^pi product (J-apply),
  * 2 Gram-Schmidt orthogonalisation + Givens update, 3 solution update,
- * 4 explicit residual, 5 value-iteration sweep, 6 other.  mask 0 disables. */
-#define IG_PROFILE_CLASSES 7
+ * 4 explicit residual, 5 value-iteration sweep, 6 other, 7 the single
+ * persistent launch of a whole solve.  mask 0 disables. */
+#define IG_PROFILE_CLASSES 8
 ig_status ig_profile_enable(ig_mdp_t mdp, unsigned mask);
 /* Sum of event-timed milliseconds and launch counts per class since the last
  * reset (synchronises on the recorded events).  ms and launches have

@@ -91,6 +91,22 @@ struct GivensState {
   double g[kMaxW + 1];
   double h[kMaxW + 1];   // current Hessenberg column (first CGS pass, then h1 + h2)
   double h2[kMaxW + 1];  // second CGS pass coefficients
+  double y[kMaxW];       // least-squares solution of the current cycle
+};
+
+// Control block of one persistent (single-launch) solve.  Zeroed before the
+// launch; the block that arrives last at a grid barrier reduces the
+// per-block partials, publishes the scalars below and releases the barrier.
+struct PCtl {
+  unsigned int count;  // arrivals at the current barrier
+  unsigned int gen;    // barrier generation
+  int32_t err;         // 1: a barrier wait exceeded its spin limit
+  int32_t dec;         // decision published by the reducer
+  double thr, inv_beta, inv_eta, eta, rho, cycle_beta;
+  double phi_inf, phi_l2sq, res_inf, res_l2sq, vmax;
+  double alg_bytes;
+  int32_t outer, inner, restarts, expl, breakdowns, stagnations, converged, bellman;
+  int32_t steps_outer, breakdown_flag, restart_req, nonfinite;
 };
 
 // Reduction context: per-block partials and a self-resetting ticket.

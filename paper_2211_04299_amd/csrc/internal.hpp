@@ -20,7 +20,7 @@ ig_status fail(ig_status s, const std::string& msg);
   } while (0)
 
 // kernel classes for the optional per-class event timing
-enum KClass { KC_BELLMAN = 0, KC_JAPPLY, KC_GS, KC_UPDATE, KC_RESID, KC_VI, KC_OTHER, KC_COUNT };
+enum KClass { KC_BELLMAN = 0, KC_JAPPLY, KC_GS, KC_UPDATE, KC_RESID, KC_VI, KC_OTHER, KC_PERSIST, KC_COUNT };
 
 struct Workspace {
   int W = 0;           // restart capacity
@@ -67,6 +67,10 @@ struct Mdp {
   GivensState* gs = nullptr;    // device
   double* part = nullptr;       // reduction partials
   unsigned int* ticket = nullptr;
+  PCtl* pctl = nullptr;         // persistent-solve control block (device)
+  PCtl* hpctl = nullptr;        // pinned host mirror
+  int num_cu = 0;
+  bool coop = false;            // cooperative launch supported
   Workspace ws;
 
   // lanes per state of the streaming kernels
@@ -122,6 +126,14 @@ void launch_residual_dense(Mdp& d, const int32_t* pi, const double* V, double* r
 void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double* Vout,
                            hipStream_t s);
 void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s);
+
+// ---- persistent single-launch solver (sparse, up to kPMaxBlocks*kPMaxSpb slices)
+// Returns IG_E_TOO_LARGE (without side effects) when the shape does not fit
+// the persistent engine; the caller then uses the stream engine.
+ig_status persistent_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& st,
+                            hipStream_t s);
+bool persistent_fits(const Mdp& d);
+int persistent_grid(const Mdp& d);
 
 // ---- Krylov (Gram-Schmidt, Givens, update) -------------------------------
 // Q_0 = r / sqrt(*l2sq); Givens state reset with g_hat = beta e_1.

@@ -107,9 +107,10 @@ void free_all(Mdp* d) {
     if (p) (void)hipFree(p);
   };
   F(d->col); F(d->val); F(d->off); F(d->width); F(d->offp); F(d->pcol); F(d->pval);
-  F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->ticket);
+  F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->ticket); F(d->pctl);
   F(d->ws.Q); F(d->ws.wA); F(d->ws.wB); F(d->ws.Vb); F(d->ws.r); F(d->ws.t); F(d->ws.pi);
   if (d->hst) (void)hipHostFree(d->hst);
+  if (d->hpctl) (void)hipHostFree(d->hpctl);
   if (d->ev0) (void)hipEventDestroy(d->ev0);
   if (d->ev1) (void)hipEventDestroy(d->ev1);
   for (auto& pool : d->prof_ev)
@@ -360,18 +361,24 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
   if (dmalloc(&d->cost, (size_t)R * 8) || dmalloc(&d->cpi, (size_t)n * 8) ||
       dmalloc(&d->st, sizeof(DevStatus)) || dmalloc(&d->gs, sizeof(GivensState)) ||
       dmalloc(&d->part, (size_t)kGsBlocks * (kMaxW + 1) * 8 + (size_t)kMaxBlocks * 8 * 8) ||
-      dmalloc(&d->ticket, 64))
+      dmalloc(&d->ticket, 64) || dmalloc(&d->pctl, sizeof(PCtl)))
     return IG_E_NOMEM;
   IG_HIP(hipMemcpy(d->cost, cost_t.data(), (size_t)R * 8, hipMemcpyHostToDevice));
   IG_HIP(hipMemset(d->st, 0, sizeof(DevStatus)));
   IG_HIP(hipMemset(d->gs, 0, sizeof(GivensState)));
   IG_HIP(hipMemset(d->ticket, 0, 64));
-  if (hipHostMalloc((void**)&d->hst, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void**)&d->hst, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&d->hpctl, sizeof(PCtl), hipHostMallocDefault) != hipSuccess)
     return fail(IG_E_NOMEM, "hipHostMalloc failed");
+  IG_HIP(hipMemset(d->pctl, 0, sizeof(PCtl)));
   std::memset(d->hst, 0, sizeof(DevStatus));
   IG_HIP(hipEventCreate(&d->ev0));
   IG_HIP(hipEventCreate(&d->ev1));
   IG_HIP(hipGetDevice(&d->device));
+  int coop = 0;
+  IG_HIP(hipDeviceGetAttribute(&d->num_cu, hipDeviceAttributeMultiprocessorCount, d->device));
+  IG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, d->device));
+  d->coop = coop != 0;
   IG_HIP(hipDeviceSynchronize());
   (void)stream;
   return IG_OK;
@@ -398,6 +405,7 @@ void ig_params_default(ig_params* p, double gamma) {
   p->opi_sweeps = 20;
   p->forcing = 0;
   p->eval_rtol = 1e-13;
+  p->engine = 0;
 }
 
 ig_status mdp_create(const ig_mdp_desc* desc, void* stream, ig_mdp_t* out) {
@@ -444,6 +452,8 @@ ig_status mdp_get_info(ig_mdp_t mdp, ig_mdp_info* info) {
   info->store = d.store;
   info->fmt = d.fmt;
   info->gamma = d.gamma;
+  info->persistent_ok = ig::persistent_fits(d) ? 1 : 0;
+  info->persistent_blocks = info->persistent_ok ? ig::persistent_grid(d) : 0;
   return IG_OK;
 }
 

@@ -221,6 +221,9 @@ ig_status bellman_pass(Mdp& d, const double* V, double* TV, int32_t* pi, const i
 ig_status run_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& st,
                      hipStream_t s) {
   const bool fp32 = p.mode == IG_MODE_MIXED;
+  if (p.engine < 0 || p.engine > 2) return fail(IG_E_INVALID, "engine must be 0, 1 or 2");
+  if (p.engine == 2 || (p.engine == 0 && persistent_fits(d)))
+    return persistent_igmres(d, V, pi, p, st, s);
   if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
   for (int k = 0;; ++k) {
     // pi_k = GreedyPolicy(V_k); Phi_k = g - J V_k = T V_k - V_k

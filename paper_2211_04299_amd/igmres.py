@@ -29,8 +29,10 @@ IG_FP64, IG_FP32, IG_BF16 = 0, 1, 2
 DTYPES = {"fp64": IG_FP64, "fp32": IG_FP32, "bf16": IG_BF16}
 IG_MODE_FP64, IG_MODE_MIXED = 0, 1
 IG_MAX_RESTART = 128
-IG_PROFILE_CLASSES = 7
-PROFILE_CLASS_NAMES = ["bellman", "japply", "gram_schmidt", "update", "residual", "vi_sweep", "other"]
+ENGINE_AUTO, ENGINE_STREAM, ENGINE_PERSISTENT = 0, 1, 2
+IG_PROFILE_CLASSES = 8
+PROFILE_CLASS_NAMES = ["bellman", "japply", "gram_schmidt", "update", "residual", "vi_sweep", "other",
+                       "persistent"]
 
 EXPORTS = ["ig_params_default", "mdp_create", "mdp_destroy", "mdp_get_info", "bellman_apply",
            "policy_eval_gmres", "igmres_pi_solve", "pi_solve", "opi_solve", "ipi_vi_solve",
@@ -47,7 +49,8 @@ class MdpDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("restart", C.c_int32), ("max_outer", C.c_int32),
                 ("max_inner", C.c_int32), ("tol", C.c_double), ("mode", C.c_int),
-                ("opi_sweeps", C.c_int32), ("forcing", C.c_int32), ("eval_rtol", C.c_double)]
+                ("opi_sweeps", C.c_int32), ("forcing", C.c_int32), ("eval_rtol", C.c_double),
+                ("engine", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -64,7 +67,8 @@ class Stats(C.Structure):
 class MdpInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("max_width", C.c_int32), ("nnz", C.c_int64),
                 ("stored_entries", C.c_int64), ("p_bytes", C.c_int64), ("store", C.c_int),
-                ("fmt", C.c_int), ("gamma", C.c_double)]
+                ("fmt", C.c_int), ("gamma", C.c_double), ("persistent_ok", C.c_int32),
+                ("persistent_blocks", C.c_int32)]
 
 
 _P = C.c_void_p

@@ -48,7 +48,7 @@ def test_ctypes_layouts_match_c(tmp_path):
         int main(void) {{
           printf("%zu %zu %zu %zu\\n", sizeof(ig_mdp_desc), sizeof(ig_params), sizeof(ig_stats),
                  sizeof(ig_mdp_info));
-          printf("%zu %zu %zu\\n", offsetof(ig_mdp_desc, validate), offsetof(ig_params, eval_rtol),
+          printf("%zu %zu %zu\\n", offsetof(ig_mdp_desc, validate), offsetof(ig_params, engine),
                  offsetof(ig_stats, alg_bytes));
           return 0;
         }}"""))
@@ -59,7 +59,7 @@ def test_ctypes_layouts_match_c(tmp_path):
     assert sizes == [ctypes.sizeof(igmres.MdpDesc), ctypes.sizeof(igmres.Params),
                      ctypes.sizeof(igmres.Stats), ctypes.sizeof(igmres.MdpInfo)]
     offs = [int(x) for x in lines[1].split()]
-    assert offs == [igmres.MdpDesc.validate.offset, igmres.Params.eval_rtol.offset,
+    assert offs == [igmres.MdpDesc.validate.offset, igmres.Params.engine.offset,
                     igmres.Stats.alg_bytes.offset]
 
 

@@ -39,11 +39,15 @@ def solve(mdp, method="igmres_pi_solve", store="fp64", V0=None, allow_noconv=Fal
         return host(V), host(pi), st
 
 
+ENGINES = [1, 2]  # one launch per step; one persistent launch per solve
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_igmres_c1_parity(seed):
+def test_igmres_c1_parity(seed, engine):
     mdp, Vs, pis = reference("c1", seed)
     tol = tol_par(mdp, np.max(np.abs(Vs)))
-    V, pi, st = solve(mdp, tol=tol, restart=20)
+    V, pi, st = solve(mdp, tol=tol, restart=20, engine=engine)
     assert st["converged"] == 1
     assert rel_err(V, Vs) <= 1e-8
     assert_policy_match(mdp, Vs, pis, pi)
@@ -54,10 +58,11 @@ def test_igmres_c1_parity(seed):
     assert abs(st["inner"] - sto.inner) <= sto.outer
 
 
-def test_igmres_c2_bench_configuration():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_igmres_c2_bench_configuration(engine):
     """The timed workload: n=1e4, m=8, k=20, gamma=0.99, W=30, tol 1e-8."""
     mdp, Vs, pis = reference("c2", 0)
-    V, pi, st = solve(mdp, tol=1e-8, restart=30)
+    V, pi, st = solve(mdp, tol=1e-8, restart=30, engine=engine)
     assert st["converged"] == 1 and st["res_inf"] <= 1e-8
     assert rel_err(V, Vs) <= 1e-8
     Vo, pio, sto = O.igmres_pi(mdp, W=30, tol=1e-8)
@@ -65,9 +70,10 @@ def test_igmres_c2_bench_configuration():
     assert abs(st["inner"] - sto.inner) <= sto.outer
 
 
-def test_igmres_c2_parity_tight():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_igmres_c2_parity_tight(engine):
     mdp, Vs, pis = reference("c2", 0)
-    V, pi, st = solve(mdp, tol=tol_par(mdp, np.max(np.abs(Vs))), restart=30)
+    V, pi, st = solve(mdp, tol=tol_par(mdp, np.max(np.abs(Vs))), restart=30, engine=engine)
     assert st["converged"] == 1
     assert rel_err(V, Vs) <= 1e-8
     assert_policy_match(mdp, Vs, pis, pi)
@@ -108,12 +114,13 @@ def test_dense_fp64_igmres():
     assert_policy_match(mdp, Vs, pis, pi)
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("store", ["fp32", "bf16"])
-def test_mixed_precision_against_stored_mdp_oracle(store):
+def test_mixed_precision_against_stored_mdp_oracle(store, engine):
     mdp = synth.config("c2", seed=1, n=3000)
     stored = mdp.with_values(val=synth.upcast_values(synth.round_values(mdp.val, store), store))
     Vs, pis, _ = O.policy_iteration(stored)
-    V, pi, st = solve(mdp, store=store, mode="mixed", restart=30,
+    V, pi, st = solve(mdp, store=store, mode="mixed", restart=30, engine=engine,
                       tol=tol_par(stored, np.max(np.abs(Vs))))
     assert st["converged"] == 1
     assert rel_err(V, Vs) <= 1e-6
@@ -142,17 +149,37 @@ def test_single_state_closed_form():
     assert pi[0] == int(np.argmin(mdp.cost))
 
 
-def test_deterministic_bits():
-    mdp, _, _ = reference("c1", 2)
-    a = solve(mdp, tol=1e-10)[0]
-    b = solve(mdp, tol=1e-10)[0]
+@pytest.mark.parametrize("engine", ENGINES)
+def test_deterministic_bits(engine):
+    mdp, _, _ = reference("c2", 0)
+    a = solve(mdp, tol=1e-10, engine=engine)[0]
+    b = solve(mdp, tol=1e-10, engine=engine)[0]
     assert np.array_equal(a, b)
 
 
-def test_noconv_and_bad_params():
+@pytest.mark.parametrize("n", [64, 65, 5000, 40000])
+def test_persistent_engine_shapes(n):
+    """Block ownership of 1, 2 and several slices per block, ragged tails."""
+    mdp = synth.sparse_uniform(n, 5, 7, 0.97, seed=n)
+    Vs, pis, _ = O.policy_iteration(mdp) if n <= 5000 else (None, None, None)
+    I = igm()
+    with I.mdp_create(mdp) as h:
+        assert h.info().persistent_ok == 1
+    Va, pia, sta = solve(mdp, tol=1e-10, engine=1)
+    Vb, pib, stb = solve(mdp, tol=1e-10, engine=2)
+    assert sta["converged"] == 1 and stb["converged"] == 1
+    assert stb["outer"] == sta["outer"]
+    assert abs(stb["inner"] - sta["inner"]) <= sta["outer"]
+    np.testing.assert_allclose(Vb, Va, rtol=1e-10)
+    if Vs is not None:
+        assert rel_err(Vb, Vs) <= 1e-8
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_noconv_and_bad_params(engine):
     I = igm()
     mdp, _, _ = reference("c1", 0)
-    V, pi, st = solve(mdp, max_outer=1, tol=1e-14, allow_noconv=True)
+    V, pi, st = solve(mdp, max_outer=1, tol=1e-14, allow_noconv=True, engine=engine)
     assert st["status"] == I.IG_E_NOCONV and st["converged"] == 0
     for kw, code in [(dict(alpha=0.0), I.IG_E_INVALID), (dict(restart=0), I.IG_E_INVALID),
                      (dict(restart=129), I.IG_E_TOO_LARGE), (dict(tol=0.0), I.IG_E_INVALID)]:
