@@ -1,45 +1,47 @@
 // Persistent single-launch GMRES(W) policy iteration (Algorithm 2) for
 // sparse MDPs that fit one cooperative grid (gfx950).
 //
-// Every block owns a fixed, contiguous range of 64-state slices for the whole
-// solve, so its rows of P, P^pi, Q, w, V stay close to its compute unit.
-// Phases are separated by grid barriers; the block that arrives last at a
-// barrier reduces the per-block partials in a fixed order, takes the
-// control-flow decision, publishes it and releases the barrier, so every
-// block follows the same path.  Barrier waits have a spin limit: a wait that
-// exceeds it flags an error and every block leaves at its next barrier.
+// Layout of the work: every block owns a fixed, contiguous range of 64-state
+// slices for the whole solve.  Phases are separated by grid barriers built
+// from one arrival word per block (each block polls all words; no shared
+// counter, so arrivals are not serialised on one address).  After a barrier
+// every block reduces the per-block partials itself, in a fixed order, and
+// runs the Givens update and the control decisions on its own copy of the
+// (tiny) least-squares state: all blocks compute bit-identical values and so
+// follow the same path without any broadcast.  Barrier waits have a spin
+// limit; a wait that exceeds it flags an error and every block leaves at its
+// next barrier.
 //
-// Per Arnoldi step: [A] q = J x over own rows (x = previous vector scaled by
-// 1/eta, gathered from the complete buffer), x stored as the next basis
-// column, dot products with the basis -> barrier; [B] first CGS correction,
-// second-pass dot products -> barrier; [C] second correction, ||w||^2 ->
-// barrier (reducer: Givens update of the Hessenberg column and the
-// stopping-test bracket).  When the bracket cannot decide, the iterate is
-// formed and the true FP64 residual evaluated (two more barriers).
+// Arnoldi step i (two barriers; classical Gram-Schmidt applied twice):
+//   [A] Q_i = (w1 - sum_j d_j Q_j) / eta_i on own rows (the second-pass
+//       correction of the previous step, applied lazily);
+//       w = J w1 / eta_i (gather of the complete w1);  c_j = <Q_j, w>, j <= i
+//   -- barrier --
+//   [B] w1 = w - sum_j c_j Q_j; d_j = <Q_j, w1>; sigma = ||w1||^2
+//   -- barrier --
+//   eta_{i+1} = sqrt(sigma - ||d||^2), column i of H = c + d.
+// Because the second-pass coefficients d are of the order of the rounding
+// error, applying J to w1 instead of to Q_{i+1} * eta_{i+1} changes the
+// product only at that order, and Pythagoras gives eta without cancellation.
+// When the residual bracket ||r||_inf <= rho <= sqrt(n) ||r||_inf cannot
+// decide the stopping test, the iterate is formed and the true FP64 residual
+// evaluated (two more barriers).
+#include <cstdlib>
+
 #include "internal.hpp"
 
 namespace ig {
 
 namespace {
 
-constexpr int kPB = 256;             // threads per block
-constexpr int kPMaxBlocks = 256;     // grid cap: the reducer tile fits LDS
-constexpr int kPMaxSpb = 32;         // slices per block cap
+constexpr int kPB = 1024;            // threads per block
+constexpr int kPWaves = kPB / kWave;
+constexpr int kPMaxBlocks = 256;
+constexpr int kPMaxSpb = 32;         // slices per block
 constexpr int kPMaxOwn = kPMaxSpb * kSlice;
-constexpr int kPStride = kMaxW + 8;  // doubles per block row of partials
+constexpr int kPMaxW = 64;           // restart cap of this engine (LDS Givens state)
+constexpr int kPStride = kPMaxW + 8; // doubles per block row of partials
 constexpr long kSpinLimit = 1L << 23;
-
-enum Dec : int32_t {
-  D_CONTINUE = 0,
-  D_DONE,
-  D_NOCONV,
-  D_ERR_NUMERIC,
-  D_NEXT,        // next Arnoldi step
-  D_EXPLICIT,    // form the iterate and test the true residual
-  D_END_INNER,   // inner loop finished: next outer step
-  D_RESTART,     // restart from the explicit residual
-  D_CONT_STEP,   // explicit test failed mid-cycle: next Arnoldi step
-};
 
 template <typename VT, typename XT>
 struct PArgs {
@@ -55,135 +57,126 @@ struct PArgs {
   int32_t* __restrict__ pi;
   double* __restrict__ cpi;
   XT* __restrict__ Q;
-  XT* __restrict__ w0;
   XT* __restrict__ w1;
   double* __restrict__ Vb;
   double* __restrict__ r;
-  double* __restrict__ part;
-  GivensState* __restrict__ gs;
+  double* __restrict__ part;         // [2][gridDim.x][kPStride], by barrier parity
+  unsigned int* __restrict__ flags;  // [gridDim.x] arrival epochs
   PCtl* __restrict__ ctl;
   double alpha, tol, sqrt_n;
   int W, max_outer, max_inner, forcing;
-  // algorithmic bytes per event, for the statistics
-  double b_bellman, b_japply, b_vec, b_resid;
+  double b_bellman, b_japply, b_vec, b_resid;  // algorithmic bytes per event
 };
 
-struct Pub {  // scalars every block reads after a barrier
-  int32_t dec;
-  double thr, inv_beta, inv_eta;
+// least-squares state of the current restart cycle (per block, LDS)
+struct Lsq {
+  double R[(kPMaxW + 1) * kPMaxW];  // column-major, leading dim kPMaxW+1
+  double cs[kPMaxW], sn[kPMaxW], g[kPMaxW + 1], y[kPMaxW];
+  double c[kPMaxW + 2], d[kPMaxW + 1];
 };
+
+struct Scal {  // per-block copies of the solver scalars (identical in every block)
+  double thr, beta, cycle_beta, eta, inv_eta, rho, phi_inf, res_inf, res_l2sq, alg_bytes;
+  int dec, outer, inner, steps_outer, restarts, expl, breakdowns, stagnations, bellman, converged,
+      nonfinite;
+};
+
+enum : int { D_NEXT = 0, D_EXPLICIT, D_END_INNER, D_RESTART, D_CONT, D_DONE, D_NOCONV, D_ERR };
 
 __device__ __forceinline__ int logical_block() {
-  // consecutive hardware blocks go round-robin over the 8 XCDs: give each XCD
-  // a contiguous range of slices
   const int nb = gridDim.x, b = blockIdx.x;
-  if (nb % 8 != 0) return b;
+  if (nb % 8 != 0) return b;  // round-robin XCD dispatch: contiguous slices per XCD
   return (b % 8) * (nb / 8) + b / 8;
 }
 
-__device__ __forceinline__ unsigned ld_acq(const unsigned* p) {
+__device__ __forceinline__ unsigned ld_flag(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier.  `reducer` runs in the last block to arrive (all its threads)
-// before the release.  Returns false (uniformly per block) if the solve must
-// be abandoned.
-template <typename F>
-__device__ __forceinline__ bool pbarrier(PCtl* ctl, Pub& pub, F&& reducer) {
-  __shared__ unsigned s_gen;
-  __shared__ int s_last, s_ok;
-  __shared__ Pub s_pub;
+// Grid barrier on per-block arrival words.  Returns false (uniformly in the
+// block) if any wait exceeded the spin limit.
+__device__ __forceinline__ bool gbarrier(unsigned int* flags, PCtl* ctl, unsigned epoch) {
+  __shared__ int s_ok;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned g = ld_acq(&ctl->gen);
-    __threadfence();
-    const unsigned a = atomicAdd(&ctl->count, 1u);
-    s_gen = g;
-    s_last = (a == gridDim.x - 1);
-    if (s_last) {
-      __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-    }
-  }
-  __syncthreads();
-  if (s_last) {
-    reducer();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < gridDim.x) {
     long spins = 0;
-    while (ld_acq(&ctl->gen) == s_gen) {
+    while (ld_flag(&flags[threadIdx.x]) < epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) {
         __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
-    __threadfence();
-  }
-  if (threadIdx.x == 0) {
-    s_ok = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-    s_pub.dec = ctl->dec;
-    s_pub.thr = ctl->thr;
-    s_pub.inv_beta = ctl->inv_beta;
-    s_pub.inv_eta = ctl->inv_eta;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  pub = s_pub;
+  if (threadIdx.x == 0)
+    s_ok = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+  __syncthreads();
   return s_ok != 0;
 }
 
-// Sum (or max, per bit of maxmask for columns < 32) of part[b][c] over
-// blocks, c < cnt, into dst[c]; fixed order.  All threads of the block.
-__device__ void reduce_cols(const double* __restrict__ part, int cnt, unsigned maxmask,
-                            double* __restrict__ dst) {
-  __shared__ double tile[kPMaxBlocks * 32];
-  __shared__ double seg[8 * 32];
+// out[c] = sum (or max, maxmask bit c) over blocks of part[b][c], c < cnt;
+// fixed order; all threads; result in LDS `out`.
+__device__ void reduce_rows(const double* __restrict__ part, int cnt, unsigned maxmask,
+                            double* __restrict__ out) {
+  __shared__ double seg[16][64];
   const int nb = gridDim.x;
-  for (int c0 = 0; c0 < cnt; c0 += 32) {
-    const int cw = min(32, cnt - c0);
-    for (int e = threadIdx.x; e < nb * 32; e += kPB) {
-      const int b = e >> 5, c = e & 31;
-      tile[e] = c < cw ? part[(int64_t)b * kPStride + c0 + c] : 0.0;
-    }
-    __syncthreads();
-    const int c = threadIdx.x & 31, q = threadIdx.x >> 5;
-    const bool mx = c0 == 0 && ((maxmask >> c) & 1u);
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const bool mx = c0 == 0 && c < 32 && ((maxmask >> c) & 1u);
     double acc = 0.0;
-    for (int b = q; b < nb; b += 8) acc = mx ? fmax(acc, tile[b * 32 + c]) : acc + tile[b * 32 + c];
-    seg[q * 32 + c] = acc;
+    if (c0 + c < cnt)
+      for (int b = q; b < nb; b += 16) {
+        const double x = part[(int64_t)b * kPStride + c0 + c];
+        acc = mx ? fmax(acc, x) : acc + x;
+      }
+    seg[q][c] = acc;
     __syncthreads();
-    if (threadIdx.x < cw) {
-      double a = seg[threadIdx.x];
-      for (int k = 1; k < 8; ++k) a = mx ? fmax(a, seg[k * 32 + threadIdx.x]) : a + seg[k * 32 + threadIdx.x];
-      dst[c0 + threadIdx.x] = a;
+    if (threadIdx.x < 64 && c0 + threadIdx.x < cnt) {
+      double a = seg[0][threadIdx.x];
+      for (int k = 1; k < 16; ++k) a = mx ? fmax(a, seg[k][threadIdx.x]) : a + seg[k][threadIdx.x];
+      out[c0 + threadIdx.x] = a;
     }
     __syncthreads();
   }
 }
 
 template <int NV>
-__device__ __forceinline__ void write_partials(double (&v)[NV], const int (&op)[NV], double* mypart) {
-  block_reduce<NV>(v, op);
+__device__ __forceinline__ void block_reduce_big(double (&v)[NV], const int (&op)[NV],
+                                                 double* mypart) {
+  __shared__ double sh[NV][kPWaves];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = op[k] ? wave_max(v[k]) : wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) mypart[k] = v[k];
+    for (int k = 0; k < NV; ++k) {
+      double a = sh[k][0];
+      for (int w = 1; w < kPWaves; ++w) a = op[k] ? fmax(a, sh[k][w]) : a + sh[k][w];
+      mypart[k] = a;
+    }
   }
 }
 
 template <typename VT, typename XT, typename AT, int G>
 __device__ __forceinline__ AT prow_dot(const SellPi<VT>& Pp, int64_t b, int l, int g,
-                                       const XT* __restrict__ x, XT scale) {
+                                       const XT* __restrict__ x) {
   constexpr int S = kWave / G;
   const int Kb = Pp.width[b];
   const int64_t ob = Pp.off[b] + l;
   AT acc = 0;
+#pragma unroll 8
   for (int j = g; j < Kb; j += G) {
     const int64_t e = ob + ((int64_t)j << 6);
-    const XT xv = x[Pp.col[e]] * scale;
+    const XT xv = x[Pp.col[e]];
     if constexpr (sizeof(AT) == 8)
       acc = fma(to_d(Pp.val[e]), (AT)xv, acc);
     else
@@ -194,54 +187,126 @@ __device__ __forceinline__ AT prow_dot(const SellPi<VT>& Pp, int64_t b, int l, i
   return acc;
 }
 
-// partial dot products of the own rows of Q_0..Q_{i-1} with wl (LDS) into
-// mypart[0..i): groups of 8 threads per dot, 32 dots per round
+__device__ __forceinline__ int pow2_ceil(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// partial dots <Q_j, wl> (own rows) for j < cnt into mypart[0..cnt); with_norm
+// adds ||wl||^2 as mypart[cnt].  Groups of gsz threads (a power of two,
+// 8..64) per j; every thread sums a strided subset of the own rows with its
+// loads issued together, then the group reduces with shuffles.
 template <typename XT>
-__device__ __forceinline__ void own_dots(const XT* __restrict__ Q, int64_t n, int i, int64_t s_lo,
-                                         int nown, const double* __restrict__ wl, double* mypart) {
-  const int sub = threadIdx.x & 7;
-  for (int j0 = 0; j0 < i; j0 += kPB / 8) {
-    const int j = j0 + (threadIdx.x >> 3);
-    double acc = 0.0;
-    if (j < i) {
+__device__ __forceinline__ void own_dots(const XT* __restrict__ Q, int64_t n, int cnt,
+                                         int64_t s_lo, int nown, const double* __restrict__ wl,
+                                         double* mypart, bool with_norm) {
+  const int tot = cnt + (with_norm ? 1 : 0);
+  const int gsz = max(8, min(64, kPB / pow2_ceil(tot)));
+  const int sub = threadIdx.x & (gsz - 1);
+  for (int j0 = 0; j0 < tot; j0 += kPB / gsz) {
+    const int j = j0 + threadIdx.x / gsz;
+    double a0 = 0.0, a1 = 0.0;
+    if (j < cnt) {
       const XT* q = Q + (int64_t)j * n + s_lo;
-      for (int t = sub; t < nown; t += 8) acc = fma(to_d(q[t]), wl[t], acc);
+      int t = sub;
+      for (; t + gsz < nown; t += 2 * gsz) {
+        a0 = fma(to_d(q[t]), wl[t], a0);
+        a1 = fma(to_d(q[t + gsz]), wl[t + gsz], a1);
+      }
+      if (t < nown) a0 = fma(to_d(q[t]), wl[t], a0);
+    } else if (j == cnt && with_norm) {
+      for (int t = sub; t < nown; t += gsz) a0 = fma(wl[t], wl[t], a0);
     }
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 4);
-    if (sub == 0 && j < i) mypart[j] = acc;
+    double acc = a0 + a1;
+    for (int o = 1; o < gsz; o <<= 1) acc += __shfl_xor(acc, o);
+    if (sub == 0 && j < tot) mypart[j] = acc;
+  }
+}
+
+// out[t] = base[t] + sign * sum_{j<cnt} coef_j Q_j(s_lo + t) for the own rows
+// (base and out may alias, both in LDS or global through the callbacks).
+// The block splits the j range over `parts` thread groups when the own rows
+// are few, and combines the partial sums in a fixed order through LDS.
+template <typename XT, typename Base, typename Out>
+__device__ __forceinline__ void own_axpy(const XT* __restrict__ Q, int64_t n, int64_t s_lo,
+                                         int nown, int cnt, const double* __restrict__ coef,
+                                         double sign, double* psum /* LDS, kPB */, Base base,
+                                         Out out) {
+  const int parts = nown >= kPB ? 1 : max(1, min(8, kPB / pow2_ceil(nown)));
+  const int span = kPB / parts;  // states per pass
+  const int p = threadIdx.x / span, tl = threadIdx.x % span;
+  for (int t0 = 0; t0 < nown; t0 += span) {
+    const int t = t0 + tl;
+    double acc = 0.0;
+    if (t < nown) {
+      const int64_t s = s_lo + t;
+      double a0 = 0.0, a1 = 0.0;
+      int j = p;
+      for (; j + parts < cnt; j += 2 * parts) {
+        a0 = fma(coef[j], to_d(Q[(int64_t)j * n + s]), a0);
+        a1 = fma(coef[j + parts], to_d(Q[(int64_t)(j + parts) * n + s]), a1);
+      }
+      if (j < cnt) a0 = fma(coef[j], to_d(Q[(int64_t)j * n + s]), a0);
+      acc = a0 + a1;
+    }
+    if (parts > 1) {
+      psum[threadIdx.x] = acc;
+      __syncthreads();
+      if (p == 0 && t < nown) {
+        double a = psum[tl];
+        for (int q = 1; q < parts; ++q) a += psum[q * span + tl];
+        out(t, fma(sign, a, base(t)));
+      }
+      __syncthreads();
+    } else if (t < nown) {
+      out(t, fma(sign, acc, base(t)));
+    }
   }
 }
 
 template <typename VT, typename XT, int G>
 __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
-  using AT = XT;
+  using AT = XT;  // accumulation of the P^pi products inside GMRES
   constexpr int S = kWave / G;
-  constexpr int SPR = S * (kPB / kWave);  // states per round
+  constexpr int SPR = S * kPWaves;  // states per round
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int ls = lane % S, g = lane / S;
   const int lb = logical_block();
   const int64_t sl0 = (int64_t)lb * A.spb;
   const int64_t sl1 = min<int64_t>(A.nslices, sl0 + A.spb);
-  const int64_t s_lo = sl0 * kSlice, s_hi = sl1 * kSlice;  // padded own range
-  const int64_t v_hi = min<int64_t>(s_hi, A.n);            // valid own states
-  const int nown = (int)max<int64_t>(0, v_hi - s_lo);
+  const int64_t s_lo = sl0 * kSlice, s_hi = sl1 * kSlice;
   const int64_t n = A.n;
-  double* mypart = A.part + (int64_t)blockIdx.x * kPStride;
-  PCtl* ctl = A.ctl;
-  GivensState* gs = A.gs;
+  const int64_t v_hi = min<int64_t>(s_hi, n);
+  const int nown = (int)max<int64_t>(0, v_hi - s_lo);
+  // Partials written before barrier e are read by every block after it; a
+  // fast block may already write its next partials while a slow one still
+  // reads, so rows alternate between two buffers by barrier parity.
+  const int64_t half = (int64_t)gridDim.x * kPStride;
 
-  __shared__ double wl[kPMaxOwn];
-  __shared__ double coef[kMaxW + 1];
+  __shared__ Lsq L;
+  __shared__ Scal sc;
+  __shared__ double wl[kPMaxOwn];   // w of own rows
+  __shared__ double w1l[kPMaxOwn];  // w1 of own rows
+  __shared__ double red[kPMaxW + 8];
+  __shared__ double coef[kPMaxW + 1];
+  __shared__ double psum[kPB];
 
-  Pub pub;
-  int i = 1;
-  XT* wcur = A.w0;
-  XT* wprev = A.w1;
-  const XT* xsrc = nullptr;  // vector gathered by the next product
-  XT xscale = 1;
-  bool src_is_r = true;
+  if (threadIdx.x == 0) {
+    sc = Scal{};
+    sc.dec = D_NEXT;
+  }
+  __syncthreads();
+  unsigned epoch = 0;
+#define MYPART (A.part + ((epoch + 1) & 1) * half + (int64_t)blockIdx.x * kPStride)
+#define PARTS (A.part + (epoch & 1) * half)
+  int i = 0;           // basis vectors Q_0..Q_{i-1} formed in this cycle
+  bool from_r = true;  // the next basis vector is r / beta (cycle start)
+
+#define IG_BARRIER()                                    \
+  do {                                                  \
+    if (!gbarrier(A.flags, A.ctl, ++epoch)) goto leave; \
+  } while (0)
 
   for (int k = 0;; ++k) {
     // ---------------- Bellman pass: pi_k, Phi_k = T V_k - V_k, g^pi, P^pi
@@ -250,7 +315,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
       for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
         const int64_t s = base + ls;
         const bool valid = s < n;
-        const int64_t sc = valid ? s : n - 1;
+        const int64_t sc2 = valid ? s : n - 1;
         const int64_t b = s >> 6;
         const int l = (int)(s & 63);
         const int Kb = A.P.width[b];
@@ -260,13 +325,14 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         for (int a = g; a < A.m; a += G) {
           const int64_t bs = ob + (((int64_t)a * Kb) << 6) + l;
           double acc = 0.0;
+#pragma unroll 8
           for (int j = 0; j < Kb; ++j) {
             const int64_t e = bs + ((int64_t)j << 6);
             acc = fma(to_d(A.P.val[e]), A.V[A.P.col[e]], acc);
           }
-          const double q = A.cost[(int64_t)a * n + sc] + A.gamma * acc;
+          const double q = A.cost[(int64_t)a * n + sc2] + A.gamma * acc;
           if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;
-          if (q < best) {
+          if (q < best) {  // increasing a: lowest index wins ties
             best = q;
             besta = a;
           }
@@ -302,290 +368,237 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
       }
       double v[3] = {pmax, psum, nonfin};
       const int op[3] = {1, 0, 0};
-      write_partials<3>(v, op, mypart);
+      block_reduce_big<3>(v, op, MYPART);
     }
-    const int kk = k;
-    if (!pbarrier(ctl, pub, [&]() {
-          __shared__ double red[3];
-          reduce_cols(A.part, 3, 1u, red);
-          if (threadIdx.x == 0) {
-            ctl->bellman += 1;
-            ctl->alg_bytes += A.b_bellman;
-            ctl->phi_inf = red[0];
-            ctl->phi_l2sq = red[1];
-            ctl->outer = kk;
-            ctl->res_inf = red[0];
-            int32_t dec;
-            if (red[2] != 0.0) {
-              ctl->nonfinite = 1;
-              dec = D_ERR_NUMERIC;
-            } else if (red[0] <= A.tol) {
-              ctl->converged = 1;
-              dec = D_DONE;
-            } else if (kk >= A.max_outer) {
-              dec = D_NOCONV;
-            } else {
-              const double alpha = A.forcing ? fmin(A.alpha, sqrt(red[0])) : A.alpha;
-              const double beta = sqrt(red[1]);
-              ctl->thr = alpha * red[0];
-              ctl->cycle_beta = beta;
-              ctl->inv_beta = 1.0 / beta;
-              ctl->steps_outer = 0;
-              for (int j = 0; j <= kMaxW; ++j) gs->g[j] = 0.0;
-              gs->g[0] = beta;
-              dec = D_CONTINUE;
-            }
-            ctl->dec = dec;
-          }
-        }))
-      return;
-    if (pub.dec != D_CONTINUE) return;
+    IG_BARRIER();
+    reduce_rows(PARTS, 3, 1u, red);
+    if (threadIdx.x == 0) {
+      sc.bellman += 1;
+      sc.alg_bytes += A.b_bellman;
+      sc.outer = k;
+      sc.phi_inf = red[0];
+      if (red[2] != 0.0) {
+        sc.nonfinite = 1;
+        sc.dec = D_ERR;
+      } else if (red[0] <= A.tol) {
+        sc.converged = 1;
+        sc.dec = D_DONE;
+      } else if (k >= A.max_outer) {
+        sc.dec = D_NOCONV;
+      } else {
+        const double alpha = A.forcing ? fmin(A.alpha, sqrt(red[0])) : A.alpha;
+        sc.thr = alpha * red[0];
+        sc.beta = sqrt(red[1]);
+        sc.cycle_beta = sc.beta;
+        sc.steps_outer = 0;
+        for (int j = 0; j <= kPMaxW; ++j) L.g[j] = 0.0;
+        L.g[0] = sc.beta;
+        sc.dec = D_NEXT;
+      }
+    }
+    __syncthreads();
+    if (sc.dec != D_NEXT) goto leave;
 
-    // cycle start: Vb = V (own rows), x = Phi / beta
+    // cycle start: Vb = V on own rows; the first basis vector is r / beta
     for (int64_t s = s_lo + threadIdx.x; s < v_hi; s += kPB) A.Vb[s] = A.V[s];
-    i = 1;
-    xsrc = nullptr;
-    src_is_r = true;
-    xscale = (XT)pub.inv_beta;
-    double inv_eta = 0.0;
+    i = 0;
+    from_r = true;
 
     for (;;) {
-      // ---------------- [A] q = J x; x becomes basis column i-1
+      // ---------------- [A] form Q_i; w = J Q_i; c = Q^T w
       {
-        XT* qcol = A.Q + (int64_t)(i - 1) * n;
+        XT* qi = A.Q + (int64_t)i * n;
+        if (from_r) {
+          const double inv = 1.0 / sc.beta;
+          for (int64_t s = s_lo + threadIdx.x; s < v_hi; s += kPB)
+            qi[s] = from_d<XT>(A.r[s] * inv);
+        } else {
+          for (int j = threadIdx.x; j < i; j += kPB) coef[j] = L.d[j];
+          __syncthreads();
+          const double inv = sc.inv_eta;
+          own_axpy<XT>(A.Q, n, s_lo, nown, i, coef, -1.0, psum, [&](int t) { return w1l[t]; },
+                       [&](int t, double v) { qi[s_lo + t] = from_d<XT>(v * inv); });
+        }
+        // product: gather the complete source vector (r or w1), then scale
+        const double inv_src = from_r ? 1.0 / sc.beta : sc.inv_eta;
         for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
           const int64_t s = base + ls;
           const int64_t b = s >> 6;
           const int l = (int)(s & 63);
-          AT acc;
-          XT xs;
-          if (src_is_r) {
-            // first vector of a cycle: gathered from the FP64 residual
-            const double* rr = A.r;
-            AT a2 = 0;
-            const int Kb = A.Pp.width[b];
-            const int64_t ob = A.Pp.off[b] + l;
-            for (int j = g; j < Kb; j += G) {
-              const int64_t e = ob + ((int64_t)j << 6);
-              const XT xv = (XT)(rr[A.Pp.col[e]] * (double)xscale);
-              if constexpr (sizeof(AT) == 8)
-                a2 = fma(to_d(A.Pp.val[e]), (AT)xv, a2);
-              else
-                a2 = fmaf(to_f(A.Pp.val[e]), (AT)xv, a2);
-            }
-#pragma unroll
-            for (int o = S; o < kWave; o <<= 1) a2 += __shfl_xor(a2, o);
-            acc = a2;
-            xs = s < n ? (XT)(rr[s] * (double)xscale) : (XT)0;
+          double wv;
+          if (from_r) {
+            const double acc = prow_dot<VT, double, double, G>(A.Pp, b, l, g, A.r);
+            wv = ((s < n ? A.r[s] : 0.0) - A.gamma * acc) * inv_src;
           } else {
-            acc = prow_dot<VT, XT, AT, G>(A.Pp, b, l, g, xsrc, xscale);
-            xs = s < n ? xsrc[s] * xscale : (XT)0;
+            const AT acc = prow_dot<VT, XT, AT, G>(A.Pp, b, l, g, A.w1);
+            const AT xs = s < n ? (AT)A.w1[s] : (AT)0;
+            wv = to_d((XT)((xs - (AT)A.gamma * acc) * (AT)inv_src));
           }
-          if (s < n && g == 0) {
-            qcol[s] = xs;
-            const XT wv = (XT)((AT)xs - (AT)A.gamma * acc);
-            wcur[s] = wv;
-            wl[s - s_lo] = to_d(wv);
-          }
+          if (s < n && g == 0) wl[s - s_lo] = wv;
         }
         __syncthreads();
-        own_dots<XT>(A.Q, n, i, s_lo, nown, wl, mypart);
+        own_dots<XT>(A.Q, n, i + 1, s_lo, nown, wl, MYPART, false);
       }
-      const int ii = i;
-      if (!pbarrier(ctl, pub, [&]() {
-            reduce_cols(A.part, ii, 0u, gs->h);
-            if (threadIdx.x == 0) ctl->alg_bytes += A.b_japply + A.b_vec * (ii + 1);
-          }))
-        return;
-
-      // ---------------- [B] first correction, second-pass dots
-      for (int j = threadIdx.x; j < i; j += kPB) coef[j] = gs->h[j];
+      IG_BARRIER();
+      reduce_rows(PARTS, i + 1, 0u, L.c);
       __syncthreads();
-      for (int64_t s = s_lo + threadIdx.x; s < v_hi; s += kPB) {
-        double ws = wl[s - s_lo];
-        for (int j = 0; j < i; ++j) ws = fma(-coef[j], to_d(A.Q[(int64_t)j * n + s]), ws);
-        const XT wx = from_d<XT>(ws);
-        wcur[s] = wx;
-        wl[s - s_lo] = to_d(wx);
-      }
+      // ---------------- [B] w1 = w - Q c; d = Q^T w1; sigma = ||w1||^2
+      own_axpy<XT>(A.Q, n, s_lo, nown, i + 1, L.c, -1.0, psum, [&](int t) { return wl[t]; },
+                   [&](int t, double v) {
+                     const XT vx = from_d<XT>(v);
+                     A.w1[s_lo + t] = vx;
+                     w1l[t] = to_d(vx);
+                   });
       __syncthreads();
-      own_dots<XT>(A.Q, n, i, s_lo, nown, wl, mypart);
-      if (!pbarrier(ctl, pub, [&]() {
-            reduce_cols(A.part, ii, 0u, gs->h2);
-            if (threadIdx.x == 0) ctl->alg_bytes += A.b_vec * (2 * ii + 2);
-          }))
-        return;
-
-      // ---------------- [C] second correction, ||w||^2
-      for (int j = threadIdx.x; j < i; j += kPB) coef[j] = gs->h2[j];
-      __syncthreads();
-      {
-        double nrm = 0.0;
-        for (int64_t s = s_lo + threadIdx.x; s < v_hi; s += kPB) {
-          double ws = wl[s - s_lo];
-          for (int j = 0; j < i; ++j) ws = fma(-coef[j], to_d(A.Q[(int64_t)j * n + s]), ws);
-          const XT wx = from_d<XT>(ws);
-          wcur[s] = wx;
-          const double wd = to_d(wx);
-          nrm = fma(wd, wd, nrm);
+      own_dots<XT>(A.Q, n, i + 1, s_lo, nown, w1l, MYPART, true);
+      IG_BARRIER();
+      reduce_rows(PARTS, i + 2, 0u, red);
+      if (threadIdx.x == 0) {
+        sc.alg_bytes += A.b_japply + A.b_vec * (3.0 * (i + 1) + 4.0);
+        double dd = 0.0;
+        for (int j = 0; j <= i; ++j) {
+          L.d[j] = red[j];
+          dd = fma(red[j], red[j], dd);
         }
-        double v[1] = {nrm};
-        const int op[1] = {0};
-        write_partials<1>(v, op, mypart);
+        const double eta = sqrt(fmax(red[i + 1] - dd, 0.0));
+        // column i of H: c + d, with H(i+1, i) = eta; Givens update
+        double* h = L.c;
+        for (int j = 0; j <= i; ++j) h[j] += L.d[j];
+        h[i + 1] = eta;
+        for (int j = 0; j < i; ++j) {
+          const double t = L.cs[j] * h[j] + L.sn[j] * h[j + 1];
+          h[j + 1] = -L.sn[j] * h[j] + L.cs[j] * h[j + 1];
+          h[j] = t;
+        }
+        const double rr = hypot(h[i], h[i + 1]);
+        double cs = 1.0, sn = 0.0;
+        if (rr > 0.0) {
+          cs = h[i] / rr;
+          sn = h[i + 1] / rr;
+        }
+        L.cs[i] = cs;
+        L.sn[i] = sn;
+        h[i] = rr;
+        L.g[i + 1] = -sn * L.g[i];
+        L.g[i] = cs * L.g[i];
+        for (int j = 0; j <= i; ++j) L.R[i * (kPMaxW + 1) + j] = h[j];
+        const double rho = fabs(L.g[i + 1]);
+        sc.eta = eta;
+        sc.inv_eta = eta > 0.0 ? 1.0 / eta : 0.0;
+        sc.rho = rho;
+        sc.inner += 1;
+        sc.steps_outer += 1;
+        int dec = D_NEXT;
+        if (!isfinite(eta) || !isfinite(rho)) {
+          sc.nonfinite = 1;
+          dec = D_ERR;
+        } else if (eta == 0.0) {
+          sc.breakdowns += 1;
+          dec = D_EXPLICIT;
+        } else if (!(rho > A.sqrt_n * sc.thr) || sc.steps_outer >= A.max_inner || i + 1 == A.W) {
+          dec = D_EXPLICIT;
+        }
+        if (dec == D_EXPLICIT) {  // y = R^{-1} g_hat over the i+1 columns
+          for (int j = i; j >= 0; --j) {
+            double a = L.g[j];
+            for (int l2 = j + 1; l2 <= i; ++l2) a -= L.R[l2 * (kPMaxW + 1) + j] * L.y[l2];
+            const double dj = L.R[j * (kPMaxW + 1) + j];
+            L.y[j] = dj != 0.0 ? a / dj : 0.0;
+          }
+        }
+        sc.dec = dec;
       }
-      if (!pbarrier(ctl, pub, [&]() {
-            __shared__ double red[1];
-            reduce_cols(A.part, 1, 0u, red);
-            if (threadIdx.x == 0) {
-              ctl->alg_bytes += A.b_vec * (ii + 2);
-              const double eta = sqrt(red[0]);
-              const int col = ii - 1;
-              double* h = gs->h;
-              for (int j = 0; j < ii; ++j) h[j] += gs->h2[j];
-              h[ii] = eta;
-              for (int j = 0; j < col; ++j) {
-                const double t = gs->cs[j] * h[j] + gs->sn[j] * h[j + 1];
-                h[j + 1] = -gs->sn[j] * h[j] + gs->cs[j] * h[j + 1];
-                h[j] = t;
-              }
-              const double rr = hypot(h[col], h[col + 1]);
-              double cs = 1.0, sn = 0.0;
-              if (rr > 0.0) {
-                cs = h[col] / rr;
-                sn = h[col + 1] / rr;
-              }
-              gs->cs[col] = cs;
-              gs->sn[col] = sn;
-              h[col] = rr;
-              h[col + 1] = 0.0;
-              gs->g[col + 1] = -sn * gs->g[col];
-              gs->g[col] = cs * gs->g[col];
-              for (int j = 0; j <= col; ++j) gs->R[(int64_t)col * (kMaxW + 1) + j] = h[j];
-              const double rho = fabs(gs->g[col + 1]);
-              ctl->eta = eta;
-              ctl->rho = rho;
-              ctl->inv_eta = eta > 0.0 ? 1.0 / eta : 0.0;
-              ctl->inner += 1;
-              ctl->steps_outer += 1;
-              int32_t dec = D_NEXT;
-              ctl->breakdown_flag = 0;
-              ctl->restart_req = 0;
-              if (!isfinite(eta) || !isfinite(rho)) {
-                ctl->nonfinite = 1;
-                dec = D_ERR_NUMERIC;
-              } else if (eta == 0.0) {
-                ctl->breakdown_flag = 1;
-                ctl->breakdowns += 1;
-                dec = D_EXPLICIT;
-              } else if (!(rho > A.sqrt_n * ctl->thr) || ctl->steps_outer >= A.max_inner) {
-                dec = D_EXPLICIT;
-              } else if (ii == A.W) {
-                ctl->restart_req = 1;
-                dec = D_EXPLICIT;
-              }
-              if (dec == D_EXPLICIT) {
-                if (ii == A.W) ctl->restart_req = 1;
-                for (int j = ii - 1; j >= 0; --j) {  // R y = g_hat
-                  double a = gs->g[j];
-                  for (int l2 = j + 1; l2 < ii; ++l2) a -= gs->R[(int64_t)l2 * (kMaxW + 1) + j] * gs->y[l2];
-                  const double dj = gs->R[(int64_t)j * (kMaxW + 1) + j];
-                  gs->y[j] = dj != 0.0 ? a / dj : 0.0;
-                }
-              }
-              ctl->dec = dec;
-            }
-          }))
-        return;
-      if (pub.dec == D_ERR_NUMERIC) return;
-      inv_eta = pub.inv_eta;
-      if (pub.dec == D_NEXT) {
-        xsrc = wcur;
-        xscale = (XT)inv_eta;
-        src_is_r = false;
-        XT* t = wcur;
-        wcur = wprev;
-        wprev = t;
+      __syncthreads();
+      if (sc.dec == D_ERR) goto leave;
+      if (sc.dec == D_NEXT) {
+        from_r = false;
         ++i;
         continue;
       }
 
-      // ---------------- explicit test: V = Vb + Q y, r = g - J V (FP64)
-      for (int j = threadIdx.x; j < i; j += kPB) coef[j] = gs->y[j];
+      // ---------------- explicit test: V = Vb + Q y; r = g - J V in FP64
+      for (int j = threadIdx.x; j <= i; j += kPB) coef[j] = L.y[j];
       __syncthreads();
-      for (int64_t s = s_lo + threadIdx.x; s < v_hi; s += kPB) {
-        double v = A.Vb[s];
-        for (int j = 0; j < i; ++j) v = fma(coef[j], to_d(A.Q[(int64_t)j * n + s]), v);
-        A.V[s] = v;
-      }
-      if (!pbarrier(ctl, pub, [&]() {}))
-        return;
+      own_axpy<XT>(A.Q, n, s_lo, nown, i + 1, coef, 1.0, psum, [&](int t) { return A.Vb[s_lo + t]; },
+                   [&](int t, double v) { A.V[s_lo + t] = v; });
+      IG_BARRIER();
       {
-        double pmax = 0.0, psum = 0.0, vmax = 0.0;
+        double pmax = 0.0, psum = 0.0;
         for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
           const int64_t s = base + ls;
           const int64_t b = s >> 6;
           const int l = (int)(s & 63);
-          const double acc = prow_dot<VT, double, double, G>(A.Pp, b, l, g, A.V, 1.0);
+          const double acc = prow_dot<VT, double, double, G>(A.Pp, b, l, g, A.V);
           if (s < n && g == 0) {
             const double rr = A.cpi[s] - (A.V[s] - A.gamma * acc);
             A.r[s] = rr;
             pmax = fmax(pmax, fabs(rr));
             psum = fma(rr, rr, psum);
-            vmax = fmax(vmax, fabs(A.V[s]));
           }
         }
-        double v[3] = {pmax, psum, vmax};
-        const int op[3] = {1, 0, 1};
-        write_partials<3>(v, op, mypart);
+        double v[2] = {pmax, psum};
+        const int op[2] = {1, 0};
+        block_reduce_big<2>(v, op, MYPART);
       }
-      if (!pbarrier(ctl, pub, [&]() {
-            __shared__ double red[3];
-            reduce_cols(A.part, 3, 5u, red);
-            if (threadIdx.x == 0) {
-              ctl->alg_bytes += A.b_resid + A.b_vec * ii;
-              ctl->expl += 1;
-              ctl->res_l2sq = red[1];
-              ctl->vmax = red[2];
-              int32_t dec;
-              if (ctl->breakdown_flag || red[0] <= ctl->thr || ctl->steps_outer >= A.max_inner) {
-                dec = D_END_INNER;
-              } else if (ctl->restart_req) {
-                const double nb = sqrt(red[1]);
-                if (nb > (1.0 - 1e-6) * ctl->cycle_beta) {
-                  ctl->stagnations += 1;
-                  dec = D_END_INNER;
-                } else {
-                  ctl->cycle_beta = nb;
-                  ctl->inv_beta = 1.0 / nb;
-                  ctl->restarts += 1;
-                  for (int j = 0; j <= kMaxW; ++j) gs->g[j] = 0.0;
-                  gs->g[0] = nb;
-                  dec = D_RESTART;
-                }
-              } else {
-                dec = D_CONT_STEP;
-              }
-              ctl->dec = dec;
-            }
-          }))
-        return;
-      if (pub.dec == D_END_INNER) break;
-      if (pub.dec == D_RESTART) {
+      IG_BARRIER();
+      reduce_rows(PARTS, 2, 1u, red);
+      if (threadIdx.x == 0) {
+        sc.alg_bytes += A.b_resid + A.b_vec * (i + 3.0);
+        sc.expl += 1;
+        sc.res_inf = red[0];
+        sc.res_l2sq = red[1];
+        int dec;
+        if (sc.eta == 0.0 || red[0] <= sc.thr || sc.steps_outer >= A.max_inner) {
+          dec = D_END_INNER;
+        } else if (i + 1 == A.W) {
+          const double nb = sqrt(red[1]);
+          if (nb > (1.0 - 1e-6) * sc.cycle_beta) {
+            sc.stagnations += 1;
+            dec = D_END_INNER;
+          } else {
+            sc.cycle_beta = nb;
+            sc.beta = nb;
+            sc.restarts += 1;
+            for (int j = 0; j <= kPMaxW; ++j) L.g[j] = 0.0;
+            L.g[0] = nb;
+            dec = D_RESTART;
+          }
+        } else {
+          dec = D_CONT;
+        }
+        sc.dec = dec;
+      }
+      __syncthreads();
+      if (sc.dec == D_END_INNER) break;
+      if (sc.dec == D_RESTART) {
         for (int64_t s = s_lo + threadIdx.x; s < v_hi; s += kPB) A.Vb[s] = A.V[s];
-        i = 1;
-        src_is_r = true;
-        xscale = (XT)pub.inv_beta;
+        i = 0;
+        from_r = true;
         continue;
       }
-      // D_CONT_STEP
-      xsrc = wcur;
-      xscale = (XT)inv_eta;
-      src_is_r = false;
-      XT* t = wcur;
-      wcur = wprev;
-      wprev = t;
+      from_r = false;  // D_CONT
       ++i;
     }
+  }
+
+leave:
+#undef IG_BARRIER
+#undef MYPART
+#undef PARTS
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    PCtl* c = A.ctl;
+    c->outer = sc.outer;
+    c->inner = sc.inner;
+    c->restarts = sc.restarts;
+    c->expl = sc.expl;
+    c->breakdowns = sc.breakdowns;
+    c->stagnations = sc.stagnations;
+    c->converged = sc.converged;
+    c->bellman = sc.bellman;
+    c->nonfinite = sc.nonfinite;
+    c->phi_inf = sc.phi_inf;
+    c->alg_bytes = sc.alg_bytes;
+    c->dec = sc.dec;
   }
 }
 
@@ -598,9 +611,24 @@ ig_status launch_persist(Mdp& d, const PArgs<VT, XT>& a, int nblocks, hipStream_
   return IG_OK;
 }
 
+int persistent_blocks(const Mdp& d, int* spb_out) {
+  int want = (int)std::max<int64_t>(1, std::min<int64_t>(d.nslices, d.nslices / 4));
+  if (const char* e = std::getenv("IG_PERSIST_BLOCKS")) want = std::max(1, std::atoi(e));
+  if (want >= 16) want = want / 8 * 8;  // whole XCD groups
+  const int cap = std::min(kPMaxBlocks, std::max(1, d.num_cu));
+  int nb = (int)std::min<int64_t>(std::min<int64_t>(d.nslices, cap), want);
+  nb = std::max(nb, (int)((d.nslices + kPMaxSpb - 1) / kPMaxSpb));
+  nb = std::min(nb, cap);
+  const int spb = (int)((d.nslices + nb - 1) / nb);
+  nb = (int)((d.nslices + spb - 1) / spb);
+  *spb_out = spb;
+  return nb;
+}
+
 template <typename VT, typename XT>
-ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, int nblocks, int spb,
-                    hipStream_t s) {
+ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, hipStream_t s) {
+  int spb = 0;
+  const int nb = persistent_blocks(d, &spb);
   PArgs<VT, XT> a;
   a.P = SellP<VT>{d.col, (const VT*)d.val, d.off, d.width};
   a.Pp = SellPi<VT>{d.pcol, (VT*)d.pval, d.offp, d.width};
@@ -614,12 +642,11 @@ ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, int nblo
   a.pi = pi;
   a.cpi = d.cpi;
   a.Q = (XT*)d.ws.Q;
-  a.w0 = (XT*)d.ws.wA;
-  a.w1 = (XT*)d.ws.wB;
+  a.w1 = (XT*)d.ws.wA;
   a.Vb = d.ws.Vb;
   a.r = d.ws.r;
   a.part = d.part;
-  a.gs = d.gs;
+  a.flags = (unsigned int*)d.ws.wB;  // arrival words, zeroed below
   a.ctl = d.pctl;
   a.alpha = p.alpha;
   a.tol = p.tol;
@@ -630,24 +657,20 @@ ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, int nblo
   a.forcing = p.forcing;
   const double entry = d.vb + 4.0, xb = sizeof(XT);
   a.b_bellman = d.nnz * entry + d.n * (double)d.m * 8 + d.n * 28.0;
-  a.b_japply = (double)d.nnz / d.m * entry + d.n * xb * 3;
+  a.b_japply = (double)d.nnz / d.m * entry + d.n * xb * 2;
   a.b_vec = d.n * xb;
   a.b_resid = (double)d.nnz / d.m * entry + d.n * 24.0;
-  const int G = spb == 1 ? 4 : (spb == 2 ? 2 : 1);
+  IG_HIP(hipMemsetAsync(a.flags, 0, (size_t)nb * sizeof(unsigned), s));
+  // lanes per state: every thread busy on the own slices
+  const int per_state = kPB / (kSlice * spb);
+  const int G = per_state >= 16 ? 16 : per_state >= 8 ? 8 : per_state >= 4 ? 4 : per_state >= 2 ? 2 : 1;
   switch (G) {
-    case 4: return launch_persist<VT, XT, 4>(d, a, nblocks, s);
-    case 2: return launch_persist<VT, XT, 2>(d, a, nblocks, s);
-    default: return launch_persist<VT, XT, 1>(d, a, nblocks, s);
+    case 16: return launch_persist<VT, XT, 16>(d, a, nb, s);
+    case 8: return launch_persist<VT, XT, 8>(d, a, nb, s);
+    case 4: return launch_persist<VT, XT, 4>(d, a, nb, s);
+    case 2: return launch_persist<VT, XT, 2>(d, a, nb, s);
+    default: return launch_persist<VT, XT, 1>(d, a, nb, s);
   }
-}
-
-int persistent_blocks(const Mdp& d, int* spb_out) {
-  const int cap = std::min(kPMaxBlocks, std::max(1, d.num_cu));
-  int nb = (int)std::min<int64_t>(d.nslices, cap);
-  int spb = (int)((d.nslices + nb - 1) / nb);
-  nb = (int)((d.nslices + spb - 1) / spb);
-  *spb_out = spb;
-  return nb;
 }
 
 }  // namespace
@@ -661,30 +684,26 @@ bool persistent_fits(const Mdp& d) {
   if (d.fmt != IG_FMT_CSR || !d.coop || d.num_cu <= 0) return false;
   int spb = 0;
   persistent_blocks(d, &spb);
-  return spb <= kPMaxSpb;
+  return spb <= kPMaxSpb && d.n >= 1;
 }
 
 ig_status persistent_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& st,
                             hipStream_t s) {
   if (!persistent_fits(d)) return fail(IG_E_TOO_LARGE, "shape does not fit the persistent engine");
+  if (p.restart > kPMaxW) return fail(IG_E_TOO_LARGE, "the persistent engine takes restart <= 64");
   const bool fp32 = p.mode == IG_MODE_MIXED;
   if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
-  int spb = 0;
-  const int nb = persistent_blocks(d, &spb);
   IG_HIP(hipMemsetAsync(d.pctl, 0, sizeof(PCtl), s));
   ig_status e;
   switch (d.store) {
     case IG_FP64:
-      e = fp32 ? run_typed<double, float>(d, V, pi, p, nb, spb, s)
-               : run_typed<double, double>(d, V, pi, p, nb, spb, s);
+      e = fp32 ? run_typed<double, float>(d, V, pi, p, s) : run_typed<double, double>(d, V, pi, p, s);
       break;
     case IG_FP32:
-      e = fp32 ? run_typed<float, float>(d, V, pi, p, nb, spb, s)
-               : run_typed<float, double>(d, V, pi, p, nb, spb, s);
+      e = fp32 ? run_typed<float, float>(d, V, pi, p, s) : run_typed<float, double>(d, V, pi, p, s);
       break;
     default:
-      e = fp32 ? run_typed<bf16, float>(d, V, pi, p, nb, spb, s)
-               : run_typed<bf16, double>(d, V, pi, p, nb, spb, s);
+      e = fp32 ? run_typed<bf16, float>(d, V, pi, p, s) : run_typed<bf16, double>(d, V, pi, p, s);
       break;
   }
   if (e) return e;

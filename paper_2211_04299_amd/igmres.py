@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libigmres.so")
+LIB_PATH = os.environ.get("IGMRES_LIB") or os.path.join(HERE, "libigmres.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2211_04299_amd.build`")
