@@ -113,7 +113,9 @@ typedef struct {
 
 typedef struct {
   int32_t outer;          /* outer iterations performed (Bellman passes - 1)  */
-  int32_t inner;          /* Arnoldi steps (P^pi products inside GMRES)       */
+  int32_t inner;          /* Arnoldi steps of the returned iterates (the stop
+                             test of a column is known one step later; that
+                             speculative step is not counted)                */
   int32_t restarts;
   int32_t bellman_passes;
   int32_t explicit_residuals; /* true-residual evaluations made for the

@@ -79,6 +79,7 @@ struct DevStatus {
   double beta;        // 2-norm of the residual that started the cycle
   double aux;         // kernel-specific scalar (e.g. VI sweep difference)
   double vmax;        // ||V||_inf seen by the last residual pass
+  double res_impl;    // ||Q z||_inf: residual of the previous column's iterate
   int32_t nonfinite;  // NaN/Inf seen in the last Bellman pass
   int32_t changes;    // policy entries changed by the last improvement
 
@@ -90,8 +91,9 @@ struct GivensState {
   double sn[kMaxW];
   double g[kMaxW + 1];
   double h[kMaxW + 1];   // current Hessenberg column (first CGS pass, then h1 + h2)
-  double h2[kMaxW + 1];  // second CGS pass coefficients
+  double h2[kMaxW + 1];  // second CGS pass coefficients (applied lazily)
   double y[kMaxW];       // least-squares solution of the current cycle
+  double z[kMaxW + 2];   // residual of the LSQ problem in basis coordinates
 };
 
 // Control block of one persistent (single-launch) solve.  Zeroed before the
@@ -109,10 +111,9 @@ struct PCtl {
   int32_t steps_outer, breakdown_flag, restart_req, nonfinite;
 };
 
-// Reduction context: per-block partials and a self-resetting ticket.
+// Reduction context: per-block partials of the last finishing kernel.
 struct RedCtx {
-  double* part;        // [gridDim.x * nv]
-  unsigned int* ticket;
+  double* part;  // [gridDim.x * nv]
 };
 
 // ---------------------------------------------------------------------------
@@ -152,36 +153,20 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV
   __syncthreads();
 }
 
-// Write this block's partials; return true in the block that finished last
-// (all threads of that block), after which finish_partials() may read all.
+// Block partials for a finishing kernel: block_reduce, then thread 0 stores
+// the NV values at part[blockIdx.x * NV + k].  The reduction over blocks is
+// done by a one-block kernel launched next on the same stream (the kernel
+// boundary makes every block's partials visible; no fences or atomics).
 template <int NV>
-__device__ __forceinline__ bool publish_partials(const double (&v)[NV], RedCtx red) {
-  __shared__ bool last;
+__device__ __forceinline__ void store_partials(double (&v)[NV], const int (&op)[NV], double* part) {
+  block_reduce<NV>(v, op);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) red.part[blockIdx.x * NV + k] = v[k];
-    __threadfence();
-    unsigned t = atomicInc(red.ticket, gridDim.x - 1);  // wraps to 0 for the next launch
-    last = (t == gridDim.x - 1);
+    for (int k = 0; k < NV; ++k) part[(int64_t)blockIdx.x * NV + k] = v[k];
   }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
 }
 
-// In the last block: reduce the nv partials of every block in a fixed order.
-template <int NV>
-__device__ __forceinline__ void finish_partials(double (&v)[NV], const int (&op)[NV], RedCtx red) {
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = 0.0;  // every reduced quantity is >= 0
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double x = red.part[b * NV + k];
-      v[k] = op[k] ? fmax(v[k], x) : v[k] + x;
-    }
-  }
-  block_reduce<NV>(v, op);
-}
+// row stride of the Gram-Schmidt partials (doubles per block)
+constexpr int kPartStride = kMaxW + 8;
 
 }  // namespace ig

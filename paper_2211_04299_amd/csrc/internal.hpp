@@ -19,6 +19,9 @@ ig_status fail(ig_status s, const std::string& msg);
       return ::ig::fail(IG_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// kinds of the one-block finishing reduction
+enum FinKind { FIN_BELLMAN = 0, FIN_RESID, FIN_VI, FIN_GATHER, FIN_IMPL, FIN_DOTS, FIN_GIVENS };
+
 // kernel classes for the optional per-class event timing
 enum KClass { KC_BELLMAN = 0, KC_JAPPLY, KC_GS, KC_UPDATE, KC_RESID, KC_VI, KC_OTHER, KC_PERSIST, KC_COUNT };
 
@@ -66,7 +69,6 @@ struct Mdp {
   DevStatus* hst = nullptr;     // pinned host mirror
   GivensState* gs = nullptr;    // device
   double* part = nullptr;       // reduction partials
-  unsigned int* ticket = nullptr;
   PCtl* pctl = nullptr;         // persistent-solve control block (device)
   PCtl* hpctl = nullptr;        // pinned host mirror
   int num_cu = 0;
@@ -95,7 +97,6 @@ struct ProfScope {
   ~ProfScope();
 };
 
-RedCtx red_ctx(Mdp& d);
 ig_status ensure_workspace(Mdp& d, int W, bool fp32);
 ig_status sync_status(Mdp& d, hipStream_t s);
 
@@ -107,9 +108,9 @@ ig_status sync_status(Mdp& d, hipStream_t s);
 void launch_bellman_sparse(Mdp& d, const double* V, double* TV, double* Phi, int32_t* pi,
                            const int32_t* pi_old, double tie_abs, bool compact, hipStream_t s);
 // y = xs - gamma P^pi xs with xs = x * scale, scale = 1/(*eta) (eta == nullptr:
-// scale 1); q_out (nullable) receives xs.  fp32: basis in float.
-void launch_japply_sparse(Mdp& d, bool fp32, const void* x, const double* eta, void* q_out,
-                          void* y, hipStream_t s);
+// scale 1).  fp32: vectors in float.
+void launch_japply_sparse(Mdp& d, bool fp32, const void* x, const double* eta, void* y,
+                          hipStream_t s);
 // r = g^pi - (V - gamma P^pi V) in FP64, with max|r| and ||r||^2 into status.
 void launch_residual_sparse(Mdp& d, const double* V, double* r, hipStream_t s);
 // Vout = g^pi + gamma P^pi Vin (FP64), max|Vout - Vin| into status.aux.
@@ -121,7 +122,7 @@ void launch_gather_policy_sparse(Mdp& d, const int32_t* pi, hipStream_t s);
 void launch_bellman_dense(Mdp& d, const double* V, double* TV, double* Phi, int32_t* pi,
                           const int32_t* pi_old, double tie_abs, hipStream_t s);
 void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* eta,
-                         void* q_out, void* y, hipStream_t s);
+                         void* y, hipStream_t s);
 void launch_residual_dense(Mdp& d, const int32_t* pi, const double* V, double* r, hipStream_t s);
 void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double* Vout,
                            hipStream_t s);
@@ -136,11 +137,23 @@ bool persistent_fits(const Mdp& d);
 int persistent_grid(const Mdp& d);
 
 // ---- Krylov (Gram-Schmidt, Givens, update) -------------------------------
+// reduce the partials of the last nb-block finishing kernel into status /
+// Givens state (cnt: number of columns for FIN_DOTS / FIN_GIVENS)
+void launch_finalize(Mdp& d, FinKind kind, int nb, hipStream_t s, int cnt = 0,
+                     bool with_impl = false);
 // Q_0 = r / sqrt(*l2sq); Givens state reset with g_hat = beta e_1.
 void launch_form_q0(Mdp& d, bool fp32, const double* r, const double* l2sq, hipStream_t s);
-// one CGS2 Arnoldi orthogonalisation of w against Q_0..Q_{i-1}, then the
-// Givens update of column i-1; eta and rho into status.
-void launch_arnoldi_orth(Mdp& d, bool fp32, int i, void* w, hipStream_t s);
+// Q_c = (w1 - sum_{j<c} h2_j Q_j) / eta and the per-block maxima of the
+// implicit residual |Q z| of column c-1 (reduced by the next launch_dots with
+// with_impl into status.res_impl)
+void launch_form_qi(Mdp& d, bool fp32, int c, const void* w1, hipStream_t s);
+// first pass (givens = false): gs->h = Q_{0..cnt-1}^T v;  second pass
+// (givens = true): d = Q^T v, sigma = ||v||^2, then the Givens update of
+// column cnt-1 (status.eta, status.rho, gs->z).
+void launch_dots(Mdp& d, bool fp32, int cnt, const void* v, bool givens, bool with_impl,
+                 hipStream_t s);
+// w1 = y - sum_{j<cnt} gs->h_j Q_j
+void launch_axpy(Mdp& d, bool fp32, int cnt, const void* y, void* w1, hipStream_t s);
 // V = Vb + sum_{j<i} y_j Q_j with R y = g_hat (back substitution per block)
 void launch_update(Mdp& d, bool fp32, int i, const double* Vb, double* V, hipStream_t s);
 

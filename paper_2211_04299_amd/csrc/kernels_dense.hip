@@ -1,7 +1,8 @@
 // Streaming kernels for dense transition data P[s][a][s'] (row-major, gfx950).
 //
 // Bellman pass: one block per state, its four wavefronts split the actions;
-// each wavefront streams a whole row with unit-stride lanes and reduces it
+// each wavefront streams whole rows with 16-byte loads per lane (when the row
+// length keeps rows 16-byte aligned), several loads in flight, and reduces
 // with shuffles; the block picks the (value, action)-lexicographic minimum.
 // Products with P^pi: one wavefront per state on row (s, pi(s)).
 #include "internal.hpp"
@@ -12,16 +13,69 @@ namespace {
 
 constexpr int kWpb = kBlock / kWave;  // wavefronts per block
 
+template <typename VT>
+struct Vec;  // 16 bytes of stored values
+template <>
+struct Vec<double> {
+  static constexpr int N = 2;
+  using T = double2;
+  __device__ static double at(const T& v, int k) { return k == 0 ? v.x : v.y; }
+};
+template <>
+struct Vec<float> {
+  static constexpr int N = 4;
+  using T = float4;
+  __device__ static double at(const T& v, int k) {
+    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
+  }
+};
+template <>
+struct Vec<bf16> {
+  static constexpr int N = 8;
+  using T = uint4;
+  __device__ static double at(const T& v, int k) {
+    const unsigned w = k < 2 ? v.x : k < 4 ? v.y : k < 6 ? v.z : v.w;
+    const unsigned bits = (k & 1) ? (w & 0xFFFF0000u) : (w << 16);
+    return (double)__uint_as_float(bits);
+  }
+};
+
+// sum_e row[e] * x[e] * scale over one row of length n, the whole wavefront
+// cooperating; AT is the accumulation type.  Result valid in every lane.
 template <typename VT, typename XT, typename AT>
 __device__ __forceinline__ AT dense_row_dot(const VT* __restrict__ row, int64_t n,
-                                            const XT* __restrict__ x, XT scale, int lane) {
+                                            const XT* __restrict__ x, XT scale, int lane,
+                                            bool vec_ok) {
   AT acc = 0;
-  for (int64_t e = lane; e < n; e += kWave) {
-    const XT xv = x[e] * scale;
-    if constexpr (sizeof(AT) == 8)
-      acc = fma(to_d(row[e]), (AT)xv, acc);
-    else
-      acc = fmaf(to_f(row[e]), (AT)xv, acc);
+  if (vec_ok) {
+    constexpr int N = Vec<VT>::N;
+    using VV = typename Vec<VT>::T;
+    const VV* rv = reinterpret_cast<const VV*>(row);
+    const int64_t nv = n / N;
+    int64_t e = lane;
+    for (; e + 3 * kWave < nv; e += 4 * kWave) {  // four 16-byte loads in flight per lane
+      VV p0 = rv[e], p1 = rv[e + kWave], p2 = rv[e + 2 * kWave], p3 = rv[e + 3 * kWave];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        acc += (AT)Vec<VT>::at(p0, k) * (AT)(x[e * N + k] * scale);
+        acc += (AT)Vec<VT>::at(p1, k) * (AT)(x[(e + kWave) * N + k] * scale);
+        acc += (AT)Vec<VT>::at(p2, k) * (AT)(x[(e + 2 * kWave) * N + k] * scale);
+        acc += (AT)Vec<VT>::at(p3, k) * (AT)(x[(e + 3 * kWave) * N + k] * scale);
+      }
+    }
+    for (; e < nv; e += kWave) {
+      VV p0 = rv[e];
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc += (AT)Vec<VT>::at(p0, k) * (AT)(x[e * N + k] * scale);
+    }
+  } else {
+    for (int64_t e = lane; e < n; e += kWave) {
+      const XT xv = x[e] * scale;
+      if constexpr (sizeof(AT) == 8)
+        acc = fma(to_d(row[e]), (AT)xv, acc);
+      else
+        acc = fmaf(to_f(row[e]), (AT)xv, acc);
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -33,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense(
     const VT* __restrict__ P, const double* __restrict__ cost, int m, int64_t n, double gamma,
     const double* __restrict__ V, double* __restrict__ TV, double* __restrict__ Phi,
     int32_t* __restrict__ pi, const int32_t* __restrict__ pi_old, double tie_abs,
-    double* __restrict__ cpi, RedCtx red, DevStatus* __restrict__ st) {
+    double* __restrict__ cpi, double* __restrict__ part, bool vec_ok) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   __shared__ double sb[kWpb], sq[kWpb];
   __shared__ int sa[kWpb];
@@ -43,10 +97,10 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense(
     double best = INFINITY, qinc = INFINITY;
     int besta = m;
     for (int a = wid; a < m; a += kWpb) {
-      const double acc =
-          dense_row_dot<VT, double, double>(P + ((int64_t)s * m + a) * n, n, V, 1.0, lane);
+      const double acc = dense_row_dot<VT, double, double>(P + ((int64_t)s * m + a) * n, n, V, 1.0,
+                                                           lane, vec_ok);
       const double q = cost[(int64_t)a * n + s] + gamma * acc;
-      if (!(q - q == 0.0)) nonfin += 1.0;
+      if (!(q - q == 0.0)) nonfin += lane == 0 ? 1.0 : 0.0;
       if (q < best) {
         best = q;
         besta = a;
@@ -94,58 +148,48 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense(
   }
   double v[4] = {pmax, psum, nonfin, chg};
   const int op[4] = {1, 0, 0, 0};
-  block_reduce<4>(v, op);
-  if (publish_partials<4>(v, red)) {
-    finish_partials<4>(v, op, red);
-    if (threadIdx.x == 0) {
-      st->phi_inf = v[0];
-      st->phi_l2sq = v[1];
-      st->nonfinite = (int32_t)v[2];
-      st->changes = (int32_t)v[3];
-    }
-  }
+  store_partials<4>(v, op, part);
 }
 
-// mode 0: y = xs - gamma P^pi xs (+ q_out = xs)
 template <typename VT, typename XT, typename AT>
 __global__ __launch_bounds__(kBlock) void k_japply_dense(const VT* __restrict__ P, int m,
                                                          int64_t n, AT gamma,
                                                          const int32_t* __restrict__ pi,
                                                          const XT* __restrict__ x,
                                                          const double* __restrict__ eta,
-                                                         XT* __restrict__ q_out,
-                                                         XT* __restrict__ y) {
+                                                         XT* __restrict__ y, bool vec_ok) {
   const int lane = threadIdx.x & (kWave - 1);
   const XT scale = eta ? (XT)(1.0 / *eta) : (XT)1;
   for (int64_t s = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; s < n;
        s += (int64_t)gridDim.x * kWpb) {
-    const AT acc = dense_row_dot<VT, XT, AT>(P + ((int64_t)s * m + pi[s]) * n, n, x, scale, lane);
+    const AT acc = dense_row_dot<VT, XT, AT>(P + ((int64_t)s * m + pi[s]) * n, n, x, scale, lane,
+                                             vec_ok);
     if (lane == 0) {
       const XT xs = x[s] * scale;
-      if (q_out) q_out[s] = xs;
       y[s] = (XT)((AT)xs - gamma * acc);
     }
   }
 }
 
-// mode 0: residual r = g^pi - (V - gamma P^pi V); mode 1: VI sweep
-// Vout = g^pi + gamma P^pi Vin with max|Vout - Vin| into status.aux.
+// MODE 0: residual r = g^pi - (V - gamma P^pi V); MODE 1: VI sweep
+// Vout = g^pi + gamma P^pi Vin.  Partials {max|.|, ||.||^2, max|V| (MODE 0)}.
 template <typename VT, int MODE>
 __global__ __launch_bounds__(kBlock) void k_policy_pass_dense(
     const VT* __restrict__ P, int m, int64_t n, double gamma, const int32_t* __restrict__ pi,
     const double* __restrict__ cpi, const double* __restrict__ V, double* __restrict__ out,
-    RedCtx red, DevStatus* __restrict__ st) {
+    double* __restrict__ part, bool vec_ok) {
   const int lane = threadIdx.x & (kWave - 1);
   double pmax = 0.0, psum = 0.0, vmax = 0.0;
   for (int64_t s = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; s < n;
        s += (int64_t)gridDim.x * kWpb) {
-    const double acc =
-        dense_row_dot<VT, double, double>(P + ((int64_t)s * m + pi[s]) * n, n, V, 1.0, lane);
+    const double acc = dense_row_dot<VT, double, double>(P + ((int64_t)s * m + pi[s]) * n, n, V,
+                                                         1.0, lane, vec_ok);
     if (lane == 0) {
       double v;
       if (MODE == 0) {
         v = cpi[s] - (V[s] - gamma * acc);
         out[s] = v;
+        vmax = fmax(vmax, fabs(V[s]));
       } else {
         const double vn = cpi[s] + gamma * acc;
         v = vn - V[s];
@@ -153,31 +197,17 @@ __global__ __launch_bounds__(kBlock) void k_policy_pass_dense(
       }
       pmax = fmax(pmax, fabs(v));
       psum = fma(v, v, psum);
-      vmax = fmax(vmax, fabs(V[s]));
     }
   }
   double v[3] = {pmax, psum, vmax};
   const int op[3] = {1, 0, 1};
-  block_reduce<3>(v, op);
-  if (publish_partials<3>(v, red)) {
-    finish_partials<3>(v, op, red);
-    if (threadIdx.x == 0) {
-      if (MODE == 0) {
-        st->res_inf = v[0];
-        st->res_l2sq = v[1];
-        st->vmax = v[2];
-      } else {
-        st->aux = v[0];
-        st->res_l2sq = v[1];
-      }
-    }
-  }
+  store_partials<3>(v, op, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_dense(const double* __restrict__ cost, int m,
                                                          int64_t n, const int32_t* __restrict__ pi,
-                                                         double* __restrict__ cpi, RedCtx red,
-                                                         DevStatus* __restrict__ st) {
+                                                         double* __restrict__ cpi,
+                                                         double* __restrict__ part) {
   double bad = 0.0;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * kBlock) {
@@ -190,11 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_dense(const double* __restric
   }
   double v[1] = {bad};
   const int op[1] = {0};
-  block_reduce<1>(v, op);
-  if (publish_partials<1>(v, red)) {
-    finish_partials<1>(v, op, red);
-    if (threadIdx.x == 0) st->changes = (int32_t)v[0];
-  }
+  store_partials<1>(v, op, part);
 }
 
 inline int grid_states(int64_t n) {
@@ -203,6 +229,11 @@ inline int grid_states(int64_t n) {
 inline int grid_waves(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + kWpb - 1) / kWpb, kMaxBlocks));
 }
+inline int grid_threads(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kMaxBlocks));
+}
+// rows of n stored values stay 16-byte aligned
+inline bool vec_ok(const Mdp& d) { return (d.n * d.vb) % 16 == 0; }
 
 template <typename F>
 void by_store(const Mdp& d, F&& f) {
@@ -217,56 +248,68 @@ void by_store(const Mdp& d, F&& f) {
 
 void launch_bellman_dense(Mdp& d, const double* V, double* TV, double* Phi, int32_t* pi,
                           const int32_t* pi_old, double tie_abs, hipStream_t s) {
-  ProfScope p(d, KC_BELLMAN, s);
-  by_store(d, [&](auto t) {
-    using VT = decltype(t);
-    hipLaunchKernelGGL(k_bellman_dense<VT>, dim3(grid_states(d.n)), dim3(kBlock), 0, s,
-                       (const VT*)d.P, (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi,
-                       pi_old, tie_abs, d.cpi, red_ctx(d), d.st);
-  });
+  {
+    ProfScope p(d, KC_BELLMAN, s);
+    by_store(d, [&](auto t) {
+      using VT = decltype(t);
+      hipLaunchKernelGGL(k_bellman_dense<VT>, dim3(grid_states(d.n)), dim3(kBlock), 0, s,
+                         (const VT*)d.P, (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi,
+                         pi_old, tie_abs, d.cpi, d.part, vec_ok(d));
+    });
+  }
+  launch_finalize(d, FIN_BELLMAN, grid_states(d.n), s);
 }
 
 void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* eta,
-                         void* q_out, void* y, hipStream_t s) {
+                         void* y, hipStream_t s) {
   ProfScope p(d, KC_JAPPLY, s);
   by_store(d, [&](auto t) {
     using VT = decltype(t);
     if (fp32)
       hipLaunchKernelGGL((k_japply_dense<VT, float, float>), dim3(grid_waves(d.n)), dim3(kBlock),
                          0, s, (const VT*)d.P, d.m, d.n, (float)d.gamma, pi, (const float*)x, eta,
-                         (float*)q_out, (float*)y);
+                         (float*)y, vec_ok(d));
     else
       hipLaunchKernelGGL((k_japply_dense<VT, double, double>), dim3(grid_waves(d.n)),
                          dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma, pi,
-                         (const double*)x, eta, (double*)q_out, (double*)y);
+                         (const double*)x, eta, (double*)y, vec_ok(d));
   });
 }
 
 void launch_residual_dense(Mdp& d, const int32_t* pi, const double* V, double* r, hipStream_t s) {
-  ProfScope p(d, KC_RESID, s);
-  by_store(d, [&](auto t) {
-    using VT = decltype(t);
-    hipLaunchKernelGGL((k_policy_pass_dense<VT, 0>), dim3(grid_waves(d.n)), dim3(kBlock), 0, s,
-                       (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, V, r,
-                       red_ctx(d), d.st);
-  });
+  {
+    ProfScope p(d, KC_RESID, s);
+    by_store(d, [&](auto t) {
+      using VT = decltype(t);
+      hipLaunchKernelGGL((k_policy_pass_dense<VT, 0>), dim3(grid_waves(d.n)), dim3(kBlock), 0, s,
+                         (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, V, r, d.part,
+                         vec_ok(d));
+    });
+  }
+  launch_finalize(d, FIN_RESID, grid_waves(d.n), s);
 }
 
 void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double* Vout,
                            hipStream_t s) {
-  ProfScope p(d, KC_VI, s);
-  by_store(d, [&](auto t) {
-    using VT = decltype(t);
-    hipLaunchKernelGGL((k_policy_pass_dense<VT, 1>), dim3(grid_waves(d.n)), dim3(kBlock), 0, s,
-                       (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, Vin, Vout,
-                       red_ctx(d), d.st);
-  });
+  {
+    ProfScope p(d, KC_VI, s);
+    by_store(d, [&](auto t) {
+      using VT = decltype(t);
+      hipLaunchKernelGGL((k_policy_pass_dense<VT, 1>), dim3(grid_waves(d.n)), dim3(kBlock), 0, s,
+                         (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, Vin, Vout,
+                         d.part, vec_ok(d));
+    });
+  }
+  launch_finalize(d, FIN_VI, grid_waves(d.n), s);
 }
 
 void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s) {
-  ProfScope p(d, KC_OTHER, s);
-  hipLaunchKernelGGL(k_gather_dense, dim3(grid_waves(d.n)), dim3(kBlock), 0, s,
-                     (const double*)d.cost, d.m, d.n, pi, d.cpi, red_ctx(d), d.st);
+  {
+    ProfScope p(d, KC_OTHER, s);
+    hipLaunchKernelGGL(k_gather_dense, dim3(grid_threads(d.n)), dim3(kBlock), 0, s,
+                       (const double*)d.cost, d.m, d.n, pi, d.cpi, d.part);
+  }
+  launch_finalize(d, FIN_GATHER, grid_threads(d.n), s);
 }
 
 }  // namespace ig

@@ -1,172 +1,155 @@
 // Arnoldi orthogonalisation, Givens-rotated Hessenberg least squares and the
-// solution update of GMRES(W) (Algorithm 2 of the paper, inner loop).
+// solution update of GMRES(W) (Algorithm 2 of the paper, inner loop), one
+// kernel launch per step.
 //
-// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2): in exact
-// arithmetic it yields the same Hessenberg column as the modified
-// Gram-Schmidt loop of Algorithm 2, with i+1 dot products per pass computed in
-// one sweep over the basis instead of i sequential sweeps.  Every dot product
-// and norm accumulates in FP64; per-block partials are combined by the last
-// block in a fixed order, so results are bitwise reproducible.
+// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2), which in
+// exact arithmetic gives the Hessenberg column of the modified Gram-Schmidt
+// loop of Algorithm 2 with one reduction per pass.  For column c:
+//   y  = J x / eta            (x = the previous once-orthogonalised vector w1)
+//   h  = Q^T y                 (k_dots + finalize)
+//   w1 = y - Q h               (k_axpy)
+//   d  = Q^T w1, sigma = ||w1||^2  (k_dots + finalize: Givens update)
+// The second-pass correction is applied lazily when the next basis vector is
+// formed, Q_{c+1} = (w1 - Q d) / eta with eta = sqrt(sigma - ||d||^2): d is of
+// the order of the rounding error, so the product J w1 / eta equals J Q_{c+1}
+// to that order and Pythagoras loses nothing.  The same pass evaluates the
+// residual of the previous column's iterate as Q z (z = the least-squares
+// residual rotated back to basis coordinates), whose infinity-norm equals the
+// true residual's in exact arithmetic.
+// Every dot product and norm accumulates in FP64; per-block partials are
+// combined by the one-block k_finalize in a fixed order.
 #include "internal.hpp"
 
 namespace ig {
 
 namespace {
 
-constexpr int kJC = 8;  // dot products accumulated per sweep
+constexpr int kJC = 8;       // dot products per sweep
+constexpr int kFinT = 1024;  // threads of the finishing kernel
 
 template <typename XT>
 __device__ __forceinline__ const XT* qcol(const XT* Q, int64_t n, int j) {
   return Q + (int64_t)j * n;
 }
 
-// partial dot products of w with Q_0..Q_{i-1} for this block's states, written
-// to part[blockIdx.x * i + j]
+// partial dot products <Q_j, v>, j < cnt, (+ ||v||^2 as column cnt when
+// with_norm), written to part[blockIdx.x * kPartStride + j]
 template <typename XT>
-__device__ __forceinline__ void block_dots(const XT* __restrict__ Q, int64_t n, int i,
-                                           const XT* __restrict__ w, double* __restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_dots(const XT* __restrict__ Q, int64_t n, int cnt,
+                                                 const XT* __restrict__ v, int with_norm,
+                                                 double* __restrict__ part) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int j0 = 0; j0 < i; j0 += kJC) {
-    double acc[kJC];
+  const int64_t s0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double* mypart = part + (int64_t)blockIdx.x * kPartStride;
+  const int op[kJC] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j0 = 0; j0 < cnt; j0 += kJC) {
+    double acc[kJC], acc2[kJC];
 #pragma unroll
-    for (int k = 0; k < kJC; ++k) acc[k] = 0.0;
-    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += stride) {
-      const double ws = to_d(w[s]);
+    for (int k = 0; k < kJC; ++k) acc[k] = acc2[k] = 0.0;
+    int64_t s = s0;
+    for (; s + stride < n; s += 2 * stride) {  // two states per thread in flight
+      const double v0 = to_d(v[s]), v1 = to_d(v[s + stride]);
 #pragma unroll
       for (int k = 0; k < kJC; ++k)
-        if (j0 + k < i) acc[k] = fma(to_d(qcol(Q, n, j0 + k)[s]), ws, acc[k]);
+        if (j0 + k < cnt) {
+          const XT* q = qcol(Q, n, j0 + k);
+          acc[k] = fma(to_d(q[s]), v0, acc[k]);
+          acc2[k] = fma(to_d(q[s + stride]), v1, acc2[k]);
+        }
     }
-    const int op[kJC] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (s < n) {
+      const double v0 = to_d(v[s]);
+#pragma unroll
+      for (int k = 0; k < kJC; ++k)
+        if (j0 + k < cnt) acc[k] = fma(to_d(qcol(Q, n, j0 + k)[s]), v0, acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kJC; ++k) acc[k] += acc2[k];
     block_reduce<kJC>(acc, op);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int k = 0; k < kJC; ++k)
-        if (j0 + k < i) part[(int64_t)blockIdx.x * i + j0 + k] = acc[k];
+        if (j0 + k < cnt) mypart[j0 + k] = acc[k];
     }
   }
-}
-
-// ticket: true in the last block to finish
-__device__ __forceinline__ bool last_block(unsigned int* ticket) {
-  __shared__ bool last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned t = atomicInc(ticket, gridDim.x - 1);
-    last = (t == gridDim.x - 1);
+  if (with_norm) {
+    double nrm[1] = {0.0};
+    for (int64_t s = s0; s < n; s += stride) {
+      const double vs = to_d(v[s]);
+      nrm[0] = fma(vs, vs, nrm[0]);
+    }
+    const int op1[1] = {0};
+    block_reduce<1>(nrm, op1);
+    if (threadIdx.x == 0) mypart[cnt] = nrm[0];
   }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
 }
 
-// in the last block: out[j] = sum_b part[b*i + j], fixed order
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int i,
-                                             double* __restrict__ out) {
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  for (int j = wid; j < i; j += kBlock / kWave) {
-    double a = 0.0;
-    for (int b = lane; b < (int)gridDim.x; b += kWave) a += part[(int64_t)b * i + j];
-    a = wave_sum(a);
-    if (lane == 0) out[j] = a;
-  }
-  __syncthreads();
-}
-
+// w1 = y - sum_{j<cnt} h_j Q_j
 template <typename XT>
-__global__ __launch_bounds__(kBlock) void k_gs_pass1(const XT* __restrict__ Q, int64_t n, int i,
-                                                     const XT* __restrict__ w,
-                                                     double* __restrict__ part,
-                                                     unsigned int* ticket,
-                                                     GivensState* __restrict__ gs) {
-  block_dots<XT>(Q, n, i, w, part);
-  if (last_block(ticket)) sum_partials(part, i, gs->h);
-}
-
-// w -= sum_j c_j Q_j with c taken from `coef`; then (pass 2) the dot products
-// of the corrected w into gs->h2.
-template <typename XT>
-__global__ __launch_bounds__(kBlock) void k_gs_pass2(const XT* __restrict__ Q, int64_t n, int i,
-                                                     XT* __restrict__ w,
-                                                     double* __restrict__ part,
-                                                     unsigned int* ticket,
-                                                     GivensState* __restrict__ gs) {
+__global__ __launch_bounds__(kBlock) void k_axpy(const XT* __restrict__ Q, int64_t n, int cnt,
+                                                 const GivensState* __restrict__ gs,
+                                                 const XT* __restrict__ y, XT* __restrict__ w1) {
   __shared__ double c[kMaxW + 1];
-  for (int j = threadIdx.x; j < i; j += kBlock) c[j] = gs->h[j];
+  for (int j = threadIdx.x; j < cnt; j += kBlock) c[j] = gs->h[j];
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += stride) {
-    double ws = to_d(w[s]);
-    for (int j = 0; j < i; ++j) ws = fma(-c[j], to_d(qcol(Q, n, j)[s]), ws);
-    w[s] = from_d<XT>(ws);
+    double a0 = to_d(y[s]), a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = 0;
+    for (; j + 4 <= cnt; j += 4) {
+      const double q0 = to_d(qcol(Q, n, j)[s]), q1 = to_d(qcol(Q, n, j + 1)[s]);
+      const double q2 = to_d(qcol(Q, n, j + 2)[s]), q3 = to_d(qcol(Q, n, j + 3)[s]);
+      a0 = fma(-c[j], q0, a0);
+      a1 = fma(-c[j + 1], q1, a1);
+      a2 = fma(-c[j + 2], q2, a2);
+      a3 = fma(-c[j + 3], q3, a3);
+    }
+    for (; j < cnt; ++j) a0 = fma(-c[j], to_d(qcol(Q, n, j)[s]), a0);
+    w1[s] = from_d<XT>((a0 + a1) + (a2 + a3));
   }
-  block_dots<XT>(Q, n, i, w, part);
-  if (last_block(ticket)) sum_partials(part, i, gs->h2);
 }
 
-// w -= sum_j h2_j Q_j; eta = ||w||_2; column i-1 of H = h + h2 with
-// H(i, i-1) = eta; apply the previous rotations, form rotation i-1, update
-// g_hat; status.eta, status.rho = |g_hat(i)|.
+// Q_c = (w1 - sum_{j<c} d_j Q_j) / eta; implicit residual of column c-1:
+// r(s) = sum_{j<=c} z_j Q_j(s); the block's max|r| goes to the spare last
+// column of its Gram-Schmidt partial row (reduced with the next dot pass).
 template <typename XT>
-__global__ __launch_bounds__(kBlock) void k_gs_pass3(const XT* __restrict__ Q, int64_t n, int i,
-                                                     XT* __restrict__ w,
-                                                     double* __restrict__ part,
-                                                     unsigned int* ticket,
-                                                     GivensState* __restrict__ gs,
-                                                     DevStatus* __restrict__ st) {
-  __shared__ double c[kMaxW + 1];
-  for (int j = threadIdx.x; j < i; j += kBlock) c[j] = gs->h2[j];
+__global__ __launch_bounds__(kBlock) void k_form_qi(XT* __restrict__ Q, int64_t n, int c,
+                                                    const XT* __restrict__ w1,
+                                                    const GivensState* __restrict__ gs,
+                                                    const DevStatus* __restrict__ st,
+                                                    double* __restrict__ part) {
+  __shared__ double dd[kMaxW + 1], zz[kMaxW + 2];
+  for (int j = threadIdx.x; j < c; j += kBlock) dd[j] = gs->h2[j];
+  for (int j = threadIdx.x; j <= c; j += kBlock) zz[j] = gs->z[j];
   __syncthreads();
+  const double inv = 1.0 / st->eta;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  double nrm[1] = {0.0};
+  double rmax = 0.0;
+  XT* qc = Q + (int64_t)c * n;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += stride) {
-    double ws = to_d(w[s]);
-    for (int j = 0; j < i; ++j) ws = fma(-c[j], to_d(qcol(Q, n, j)[s]), ws);
-    const XT wx = from_d<XT>(ws);
-    w[s] = wx;
-    const double wd = to_d(wx);
-    nrm[0] = fma(wd, wd, nrm[0]);
-  }
-  const int op[1] = {0};
-  block_reduce<1>(nrm, op);
-  if (threadIdx.x == 0) part[blockIdx.x] = nrm[0];
-  if (last_block(ticket)) {
-    __shared__ double tot;
-    if (threadIdx.x < kWave) {
-      double a = 0.0;
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += kWave) a += part[b];
-      a = wave_sum(a);
-      if (threadIdx.x == 0) tot = a;
+    double corr = 0.0, r = 0.0, corr2 = 0.0, r2 = 0.0;
+    int j = 0;
+    for (; j + 2 <= c; j += 2) {
+      const double q0 = to_d(qcol(Q, n, j)[s]), q1 = to_d(qcol(Q, n, j + 1)[s]);
+      corr = fma(dd[j], q0, corr);
+      r = fma(zz[j], q0, r);
+      corr2 = fma(dd[j + 1], q1, corr2);
+      r2 = fma(zz[j + 1], q1, r2);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const double eta = sqrt(tot);
-      const int col = i - 1;
-      double* h = gs->h;
-      for (int j = 0; j < i; ++j) h[j] += gs->h2[j];
-      h[i] = eta;
-      for (int j = 0; j < col; ++j) {  // previous rotations
-        const double t = gs->cs[j] * h[j] + gs->sn[j] * h[j + 1];
-        h[j + 1] = -gs->sn[j] * h[j] + gs->cs[j] * h[j + 1];
-        h[j] = t;
-      }
-      const double r = hypot(h[col], h[col + 1]);
-      double cs = 1.0, sn = 0.0;
-      if (r > 0.0) {
-        cs = h[col] / r;
-        sn = h[col + 1] / r;
-      }
-      gs->cs[col] = cs;
-      gs->sn[col] = sn;
-      h[col] = r;
-      h[col + 1] = 0.0;
-      gs->g[col + 1] = -sn * gs->g[col];
-      gs->g[col] = cs * gs->g[col];
-      for (int j = 0; j <= col; ++j) gs->R[(int64_t)col * (kMaxW + 1) + j] = h[j];
-      st->eta = eta;
-      st->rho = fabs(gs->g[col + 1]);
+    if (j < c) {
+      const double q0 = to_d(qcol(Q, n, j)[s]);
+      corr = fma(dd[j], q0, corr);
+      r = fma(zz[j], q0, r);
     }
+    const XT qx = from_d<XT>((to_d(w1[s]) - (corr + corr2)) * inv);
+    qc[s] = qx;
+    r = fma(zz[c], to_d(qx), r + r2);
+    rmax = fmax(rmax, fabs(r));
   }
+  double v[1] = {rmax};
+  const int op[1] = {1};
+  block_reduce<1>(v, op);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartStride + kPartStride - 1] = v[0];
 }
 
 // Q_0 = r / beta, beta = sqrt(*l2sq); Givens state reset (block 0).
@@ -210,18 +193,153 @@ __global__ __launch_bounds__(kBlock) void k_update(const XT* __restrict__ Q, int
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += stride) {
-    double v = Vb[s];
-    for (int j = 0; j < i; ++j) v = fma(y[j], to_d(qcol(Q, n, j)[s]), v);
-    V[s] = v;
+    double v0 = Vb[s], v1 = 0.0;
+    int j = 0;
+    for (; j + 2 <= i; j += 2) {
+      v0 = fma(y[j], to_d(qcol(Q, n, j)[s]), v0);
+      v1 = fma(y[j + 1], to_d(qcol(Q, n, j + 1)[s]), v1);
+    }
+    if (j < i) v0 = fma(y[j], to_d(qcol(Q, n, j)[s]), v0);
+    V[s] = v0 + v1;
   }
 }
 
-inline int gs_grid(const Mdp& d) {
+// One-block finishing kernel: reduce cnt columns of per-block partials
+// (row stride `stride`) over nb blocks in a fixed order, then write the
+// result where the kind says.
+__global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __restrict__ part,
+                                                    int nb, int cnt, int stride, unsigned maxmask,
+                                                    int with_impl, DevStatus* __restrict__ st,
+                                                    GivensState* __restrict__ gs) {
+  __shared__ double seg[16][64];
+  __shared__ double red[kMaxW + 8];
+  if (with_impl) {  // implicit residual of the previous column: max over blocks
+    __shared__ double mx[kFinT / 64];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kFinT) a = fmax(a, part[(int64_t)b * stride + stride - 1]);
+    a = wave_max(a);
+    if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = mx[0];
+      for (int w = 1; w < kFinT / 64; ++w) t = fmax(t, mx[w]);
+      st->res_impl = t;
+    }
+    __syncthreads();
+  }
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const bool mx = c0 == 0 && c < 32 && ((maxmask >> c) & 1u);
+    double acc = 0.0;
+    if (c0 + c < cnt)
+      for (int b = q; b < nb; b += 16) {
+        const double x = part[(int64_t)b * stride + c0 + c];
+        acc = mx ? fmax(acc, x) : acc + x;
+      }
+    seg[q][c] = acc;
+    __syncthreads();
+    if (threadIdx.x < 64 && c0 + threadIdx.x < cnt) {
+      double a = seg[0][threadIdx.x];
+      for (int k = 1; k < 16; ++k) a = mx ? fmax(a, seg[k][threadIdx.x]) : a + seg[k][threadIdx.x];
+      red[c0 + threadIdx.x] = a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  switch (kind) {
+    case FIN_BELLMAN:
+      st->phi_inf = red[0];
+      st->phi_l2sq = red[1];
+      st->nonfinite = (int32_t)red[2];
+      st->changes = (int32_t)red[3];
+      break;
+    case FIN_RESID:
+      st->res_inf = red[0];
+      st->res_l2sq = red[1];
+      st->vmax = red[2];
+      break;
+    case FIN_VI:
+      st->aux = red[0];
+      st->res_l2sq = red[1];
+      break;
+    case FIN_GATHER:
+      st->changes = (int32_t)red[0];
+      break;
+    case FIN_IMPL:
+      st->res_impl = red[0];
+      break;
+    case FIN_DOTS:
+      for (int j = 0; j < cnt; ++j) gs->h[j] = red[j];
+      break;
+    case FIN_GIVENS: {
+      // red = [d_0..d_col, sigma]; gs->h = first-pass coefficients of column col
+      const int col = cnt - 2;
+      double dd = 0.0;
+      for (int j = 0; j <= col; ++j) {
+        gs->h2[j] = red[j];
+        dd = fma(red[j], red[j], dd);
+      }
+      const double eta = sqrt(fmax(red[col + 1] - dd, 0.0));
+      double* h = gs->h;
+      for (int j = 0; j <= col; ++j) h[j] += red[j];
+      h[col + 1] = eta;
+      for (int j = 0; j < col; ++j) {  // previous rotations
+        const double t = gs->cs[j] * h[j] + gs->sn[j] * h[j + 1];
+        h[j + 1] = -gs->sn[j] * h[j] + gs->cs[j] * h[j + 1];
+        h[j] = t;
+      }
+      const double r = hypot(h[col], h[col + 1]);
+      double cs = 1.0, sn = 0.0;
+      if (r > 0.0) {
+        cs = h[col] / r;
+        sn = h[col + 1] / r;
+      }
+      gs->cs[col] = cs;
+      gs->sn[col] = sn;
+      h[col] = r;
+      h[col + 1] = 0.0;
+      gs->g[col + 1] = -sn * gs->g[col];
+      gs->g[col] = cs * gs->g[col];
+      for (int j = 0; j <= col; ++j) gs->R[(int64_t)col * (kMaxW + 1) + j] = h[j];
+      // residual of this column's iterate in basis coordinates
+      double v = gs->g[col + 1];
+      for (int j = col; j >= 0; --j) {
+        gs->z[j + 1] = gs->cs[j] * v;
+        v = -gs->sn[j] * v;
+      }
+      gs->z[0] = v;
+      st->eta = eta;
+      st->rho = fabs(gs->g[col + 1]);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+inline int gs_grid(const Mdp& d) {  // grid-stride kernels
   const int64_t blocks = (d.n + kBlock - 1) / kBlock;
   return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, kGsBlocks));
 }
 
+
 }  // namespace
+
+void launch_finalize(Mdp& d, FinKind kind, int nb, hipStream_t s, int cnt, bool with_impl) {
+  int stride = 0;
+  unsigned mask = 0;
+  switch (kind) {
+    case FIN_BELLMAN: cnt = 4; stride = 4; mask = 1u; break;
+    case FIN_RESID: cnt = 3; stride = 3; mask = 5u; break;
+    case FIN_VI: cnt = 3; stride = 3; mask = 5u; break;
+    case FIN_GATHER: cnt = 1; stride = 1; mask = 0u; break;
+    case FIN_IMPL: cnt = 1; stride = 1; mask = 1u; break;
+    case FIN_DOTS: stride = kPartStride; mask = 0u; break;
+    case FIN_GIVENS: stride = kPartStride; mask = 0u; break;
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinT), 0, s, (int)kind, (const double*)d.part, nb,
+                     cnt, stride, mask, with_impl ? 1 : 0, d.st, d.gs);
+}
 
 void launch_form_q0(Mdp& d, bool fp32, const double* r, const double* l2sq, hipStream_t s) {
   ProfScope p(d, KC_OTHER, s);
@@ -233,26 +351,42 @@ void launch_form_q0(Mdp& d, bool fp32, const double* r, const double* l2sq, hipS
                        (double*)d.ws.Q, d.gs, d.st);
 }
 
-void launch_arnoldi_orth(Mdp& d, bool fp32, int i, void* w, hipStream_t s) {
+void launch_form_qi(Mdp& d, bool fp32, int c, const void* w1, hipStream_t s) {
   ProfScope p(d, KC_GS, s);
-  const dim3 grid(gs_grid(d)), block(kBlock);
-  if (fp32) {
-    const float* Q = (const float*)d.ws.Q;
-    hipLaunchKernelGGL(k_gs_pass1<float>, grid, block, 0, s, Q, d.n, i, (const float*)w, d.part,
-                       d.ticket, d.gs);
-    hipLaunchKernelGGL(k_gs_pass2<float>, grid, block, 0, s, Q, d.n, i, (float*)w, d.part,
-                       d.ticket, d.gs);
-    hipLaunchKernelGGL(k_gs_pass3<float>, grid, block, 0, s, Q, d.n, i, (float*)w, d.part,
-                       d.ticket, d.gs, d.st);
-  } else {
-    const double* Q = (const double*)d.ws.Q;
-    hipLaunchKernelGGL(k_gs_pass1<double>, grid, block, 0, s, Q, d.n, i, (const double*)w,
-                       d.part, d.ticket, d.gs);
-    hipLaunchKernelGGL(k_gs_pass2<double>, grid, block, 0, s, Q, d.n, i, (double*)w, d.part,
-                       d.ticket, d.gs);
-    hipLaunchKernelGGL(k_gs_pass3<double>, grid, block, 0, s, Q, d.n, i, (double*)w, d.part,
-                       d.ticket, d.gs, d.st);
+  if (fp32)
+    hipLaunchKernelGGL(k_form_qi<float>, dim3(gs_grid(d)), dim3(kBlock), 0, s, (float*)d.ws.Q,
+                       d.n, c, (const float*)w1, (const GivensState*)d.gs, (const DevStatus*)d.st,
+                       d.part);
+  else
+    hipLaunchKernelGGL(k_form_qi<double>, dim3(gs_grid(d)), dim3(kBlock), 0, s, (double*)d.ws.Q,
+                       d.n, c, (const double*)w1, (const GivensState*)d.gs, (const DevStatus*)d.st,
+                       d.part);
+}
+
+void launch_dots(Mdp& d, bool fp32, int cnt, const void* v, bool givens, bool with_impl,
+                 hipStream_t s) {
+  {
+    ProfScope p(d, KC_GS, s);
+    if (fp32)
+      hipLaunchKernelGGL(k_dots<float>, dim3(gs_grid(d)), dim3(kBlock), 0, s,
+                         (const float*)d.ws.Q, d.n, cnt, (const float*)v, givens ? 1 : 0, d.part);
+    else
+      hipLaunchKernelGGL(k_dots<double>, dim3(gs_grid(d)), dim3(kBlock), 0, s,
+                         (const double*)d.ws.Q, d.n, cnt, (const double*)v, givens ? 1 : 0, d.part);
   }
+  launch_finalize(d, givens ? FIN_GIVENS : FIN_DOTS, gs_grid(d), s, givens ? cnt + 1 : cnt,
+                  with_impl);
+}
+
+void launch_axpy(Mdp& d, bool fp32, int cnt, const void* y, void* w1, hipStream_t s) {
+  ProfScope p(d, KC_GS, s);
+  if (fp32)
+    hipLaunchKernelGGL(k_axpy<float>, dim3(gs_grid(d)), dim3(kBlock), 0, s, (const float*)d.ws.Q,
+                       d.n, cnt, (const GivensState*)d.gs, (const float*)y, (float*)w1);
+  else
+    hipLaunchKernelGGL(k_axpy<double>, dim3(gs_grid(d)), dim3(kBlock), 0, s,
+                       (const double*)d.ws.Q, d.n, cnt, (const GivensState*)d.gs, (const double*)y,
+                       (double*)w1);
 }
 
 void launch_update(Mdp& d, bool fp32, int i, const double* Vb, double* V, hipStream_t s) {

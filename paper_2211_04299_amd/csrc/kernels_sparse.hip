@@ -6,18 +6,68 @@
 // Consecutive lanes of a group address consecutive states, so every value
 // and column load is a contiguous run of S elements; the G partial results of
 // a state are combined with xor-shuffles over offsets S, 2S, ..., 32.
+// Row entries are consumed eight at a time: the eight column and value loads
+// are issued before the eight dependent gathers, so every wavefront keeps
+// enough loads in flight to cover HBM latency (the number of resident
+// wavefronts is capped by the hardware, so only this raises the bytes in
+// flight).  Reductions end with per-block partials; a one-block finishing
+// kernel (launch_finalize) combines them in a fixed order.
 #include "internal.hpp"
 
 namespace ig {
 
 namespace {
 
+constexpr int kU = 8;  // entries per unrolled chunk
+
+// sum_j val[e_j] * x[col[e_j]] * scale over the entries j = g, g+G, ... < K of
+// one sliced-ELL row starting at `base` (entry j at base + (j << 6)).
+template <typename VT, typename XT, typename AT, int G>
+__device__ __forceinline__ AT ell_row(const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                      int64_t base, int K, int g, const XT* __restrict__ x,
+                                      XT scale) {
+  AT acc = 0;
+  for (int j0 = g; j0 < K; j0 += kU * G) {
+    int32_t c[kU];
+    VT v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int j = j0 + u * G;
+      if (j < K) {
+        const int64_t e = base + ((int64_t)j << 6);
+        c[u] = col[e];
+        v[u] = val[e];
+      } else {
+        c[u] = 0;
+        v[u] = VT{};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const XT xv = x[c[u]] * scale;
+      if constexpr (sizeof(AT) == 8)
+        acc = fma(to_d(v[u]), (AT)xv, acc);
+      else
+        acc = fmaf(to_f(v[u]), (AT)xv, acc);
+    }
+  }
+  return acc;
+}
+
+template <typename AT, int G>
+__device__ __forceinline__ AT group_sum(AT acc) {
+  constexpr int S = kWave / G;
+#pragma unroll
+  for (int o = S; o < kWave; o <<= 1) acc += __shfl_xor(acc, o);
+  return acc;
+}
+
 template <typename VT, int G>
 __global__ __launch_bounds__(kBlock) void k_bellman(
     SellP<VT> P, const double* __restrict__ cost, int m, int64_t n, double gamma,
     const double* __restrict__ V, double* __restrict__ TV, double* __restrict__ Phi,
     int32_t* __restrict__ pi, const int32_t* __restrict__ pi_old, double tie_abs,
-    double* __restrict__ cpi, SellPi<VT> Pp, RedCtx red, DevStatus* __restrict__ st) {
+    double* __restrict__ cpi, SellPi<VT> Pp, double* __restrict__ part) {
   constexpr int S = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
   const int ls = lane % S, g = lane / S;
@@ -33,18 +83,14 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
     const int64_t b = s >> 6;
     const int l = (int)(s & 63);
     const int Kb = P.width[b];
-    const int64_t ob = P.off[b];
+    const int64_t ob = P.off[b] + l;
     const int inc = pi_old ? pi_old[sc] : -1;
 
     double best = INFINITY, qinc = INFINITY;
     int besta = m;  // sentinel: no finite candidate yet
     for (int a = g; a < m; a += G) {
-      const int64_t base = ob + (((int64_t)a * Kb) << 6) + l;
-      double acc = 0.0;
-      for (int j = 0; j < Kb; ++j) {
-        const int64_t e = base + ((int64_t)j << 6);
-        acc = fma(to_d(P.val[e]), V[P.col[e]], acc);
-      }
+      const double acc = ell_row<VT, double, double, 1>(P.col, P.val, ob + (((int64_t)a * Kb) << 6),
+                                                        Kb, 0, V, 1.0);
       const double q = cost[(int64_t)a * n + sc] + gamma * acc;
       if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;  // NaN or +-Inf
       if (q < best) {  // actions visited in increasing order: lowest index wins ties
@@ -85,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
       if (pi_old && astar != inc) chg += 1.0;
     }
     if (Pp.col) {  // copy the chosen row into the compact P^pi (groups split j)
-      const int64_t src = ob + (((int64_t)astar * Kb) << 6) + l;
+      const int64_t src = ob + (((int64_t)astar * Kb) << 6);
       const int64_t dst = Pp.off[b] + l;
       for (int j = g; j < Kb; j += G) {
         Pp.col[dst + ((int64_t)j << 6)] = P.col[src + ((int64_t)j << 6)];
@@ -95,43 +141,15 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
   }
   double v[4] = {pmax, psum, nonfin, chg};
   const int op[4] = {1, 0, 0, 0};
-  block_reduce<4>(v, op);
-  if (publish_partials<4>(v, red)) {
-    finish_partials<4>(v, op, red);
-    if (threadIdx.x == 0) {
-      st->phi_inf = v[0];
-      st->phi_l2sq = v[1];
-      st->nonfinite = (int32_t)v[2];
-      st->changes = (int32_t)v[3];
-    }
-  }
+  store_partials<4>(v, op, part);
 }
 
-// Row sum of the compact P^pi against x*scale, groups split j; the sum is
-// complete in every lane of the state after the shuffles.
-template <typename VT, typename XT, typename AT, int G>
-__device__ __forceinline__ AT row_dot(const SellPi<VT>& Pp, int64_t ob, int Kb, int l, int g,
-                                      const XT* __restrict__ x, XT scale) {
-  constexpr int S = kWave / G;
-  AT acc = 0;
-  for (int j = g; j < Kb; j += G) {
-    const int64_t e = ob + ((int64_t)j << 6) + l;
-    const XT xv = x[Pp.col[e]] * scale;
-    if constexpr (sizeof(AT) == 8)
-      acc = fma(to_d(Pp.val[e]), (AT)xv, acc);
-    else
-      acc = fmaf(to_f(Pp.val[e]), (AT)xv, acc);
-  }
-#pragma unroll
-  for (int o = S; o < kWave; o <<= 1) acc += __shfl_xor(acc, o);
-  return acc;
-}
-
+// y = xs - gamma * P^pi xs, xs = x * scale (scale = 1/eta, or 1)
 template <typename VT, typename XT, typename AT, int G>
 __global__ __launch_bounds__(kBlock) void k_japply(SellPi<VT> Pp, int64_t n, AT gamma,
                                                    const XT* __restrict__ x,
                                                    const double* __restrict__ eta,
-                                                   XT* __restrict__ q_out, XT* __restrict__ y) {
+                                                   XT* __restrict__ y) {
   constexpr int S = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
   const int ls = lane % S, g = lane / S;
@@ -143,21 +161,23 @@ __global__ __launch_bounds__(kBlock) void k_japply(SellPi<VT> Pp, int64_t n, AT 
     const int64_t s = w * S + ls;
     const int64_t b = s >> 6;
     const int l = (int)(s & 63);
-    const AT acc = row_dot<VT, XT, AT, G>(Pp, Pp.off[b], Pp.width[b], l, g, x, scale);
+    const AT acc = group_sum<AT, G>(
+        ell_row<VT, XT, AT, G>(Pp.col, Pp.val, Pp.off[b] + l, Pp.width[b], g, x, scale));
     if (s < n && g == 0) {
       const XT xs = x[s] * scale;
-      if (q_out) q_out[s] = xs;
       y[s] = (XT)((AT)xs - gamma * acc);
     }
   }
 }
 
-template <typename VT, int G>
-__global__ __launch_bounds__(kBlock) void k_residual(SellPi<VT> Pp, int64_t n, double gamma,
-                                                     const double* __restrict__ cpi,
-                                                     const double* __restrict__ V,
-                                                     double* __restrict__ r, RedCtx red,
-                                                     DevStatus* __restrict__ st) {
+// MODE 0: r = g^pi - (V - gamma P^pi V), partials {max|r|, ||r||^2, max|V|}
+// MODE 1: Vout = g^pi + gamma P^pi Vin, partials {max|Vout - Vin|, ||.||^2, 0}
+template <typename VT, int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_policy_pass(SellPi<VT> Pp, int64_t n, double gamma,
+                                                        const double* __restrict__ cpi,
+                                                        const double* __restrict__ V,
+                                                        double* __restrict__ out,
+                                                        double* __restrict__ part) {
   constexpr int S = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
   const int ls = lane % S, g = lane / S;
@@ -169,74 +189,34 @@ __global__ __launch_bounds__(kBlock) void k_residual(SellPi<VT> Pp, int64_t n, d
     const int64_t s = w * S + ls;
     const int64_t b = s >> 6;
     const int l = (int)(s & 63);
-    const double acc =
-        row_dot<VT, double, double, G>(Pp, Pp.off[b], Pp.width[b], l, g, V, 1.0);
+    const double acc = group_sum<double, G>(
+        ell_row<VT, double, double, G>(Pp.col, Pp.val, Pp.off[b] + l, Pp.width[b], g, V, 1.0));
     if (s < n && g == 0) {
-      const double rr = cpi[s] - (V[s] - gamma * acc);
-      r[s] = rr;
-      pmax = fmax(pmax, fabs(rr));
-      psum = fma(rr, rr, psum);
-      vmax = fmax(vmax, fabs(V[s]));
+      double v;
+      if (MODE == 0) {
+        v = cpi[s] - (V[s] - gamma * acc);
+        out[s] = v;
+        vmax = fmax(vmax, fabs(V[s]));
+      } else {
+        const double vn = cpi[s] + gamma * acc;
+        v = vn - V[s];
+        out[s] = vn;
+      }
+      pmax = fmax(pmax, fabs(v));
+      psum = fma(v, v, psum);
     }
   }
   double v[3] = {pmax, psum, vmax};
   const int op[3] = {1, 0, 1};
-  block_reduce<3>(v, op);
-  if (publish_partials<3>(v, red)) {
-    finish_partials<3>(v, op, red);
-    if (threadIdx.x == 0) {
-      st->res_inf = v[0];
-      st->res_l2sq = v[1];
-      st->vmax = v[2];
-    }
-  }
-}
-
-template <typename VT, int G>
-__global__ __launch_bounds__(kBlock) void k_vi_sweep(SellPi<VT> Pp, int64_t n, double gamma,
-                                                     const double* __restrict__ cpi,
-                                                     const double* __restrict__ Vin,
-                                                     double* __restrict__ Vout, RedCtx red,
-                                                     DevStatus* __restrict__ st) {
-  constexpr int S = kWave / G;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int ls = lane % S, g = lane / S;
-  const int64_t nw = (n + S - 1) / S;
-  const int64_t wstride = (int64_t)gridDim.x * (kBlock / kWave);
-  double pmax = 0.0, psum = 0.0;
-  for (int64_t w = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; w < nw;
-       w += wstride) {
-    const int64_t s = w * S + ls;
-    const int64_t b = s >> 6;
-    const int l = (int)(s & 63);
-    const double acc =
-        row_dot<VT, double, double, G>(Pp, Pp.off[b], Pp.width[b], l, g, Vin, 1.0);
-    if (s < n && g == 0) {
-      const double vn = cpi[s] + gamma * acc;
-      const double dd = vn - Vin[s];
-      Vout[s] = vn;
-      pmax = fmax(pmax, fabs(dd));
-      psum = fma(dd, dd, psum);
-    }
-  }
-  double v[2] = {pmax, psum};
-  const int op[2] = {1, 0};
-  block_reduce<2>(v, op);
-  if (publish_partials<2>(v, red)) {
-    finish_partials<2>(v, op, red);
-    if (threadIdx.x == 0) {
-      st->aux = v[0];
-      st->res_l2sq = v[1];
-    }
-  }
+  store_partials<3>(v, op, part);
 }
 
 template <typename VT, int G>
 __global__ __launch_bounds__(kBlock) void k_gather_policy(SellP<VT> P, SellPi<VT> Pp,
                                                           const double* __restrict__ cost, int m,
                                                           int64_t n, const int32_t* __restrict__ pi,
-                                                          double* __restrict__ cpi, RedCtx red,
-                                                          DevStatus* __restrict__ st) {
+                                                          double* __restrict__ cpi,
+                                                          double* __restrict__ part) {
   constexpr int S = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
   const int ls = lane % S, g = lane / S;
@@ -265,11 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_policy(SellP<VT> P, SellPi<VT
   }
   double v[1] = {bad};
   const int op[1] = {0};
-  block_reduce<1>(v, op);
-  if (publish_partials<1>(v, red)) {
-    finish_partials<1>(v, op, red);
-    if (threadIdx.x == 0) st->changes = (int32_t)v[0];
-  }
+  store_partials<1>(v, op, part);
 }
 
 inline int grid_for(const Mdp& d, int G) {
@@ -316,39 +292,35 @@ struct RunBellman {
     if (!compact) pp.col = nullptr;
     hipLaunchKernelGGL((k_bellman<VT, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
                        viewP<VT>(d), (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi,
-                       pi_old, tie_abs, d.cpi, pp, red_ctx(d), d.st);
+                       pi_old, tie_abs, d.cpi, pp, d.part);
   }
 };
 
 template <typename VT, int G>
 struct RunJapply {
-  static void run(Mdp& d, bool fp32, const void* x, const double* eta, void* q_out, void* y,
-                  hipStream_t s) {
+  static void run(Mdp& d, bool fp32, const void* x, const double* eta, void* y, hipStream_t s) {
     if (fp32)
       hipLaunchKernelGGL((k_japply<VT, float, float, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
-                         viewPi<VT>(d), d.n, (float)d.gamma, (const float*)x, eta, (float*)q_out,
-                         (float*)y);
+                         viewPi<VT>(d), d.n, (float)d.gamma, (const float*)x, eta, (float*)y);
     else
       hipLaunchKernelGGL((k_japply<VT, double, double, G>), dim3(grid_for(d, G)), dim3(kBlock), 0,
-                         s, viewPi<VT>(d), d.n, d.gamma, (const double*)x, eta, (double*)q_out,
-                         (double*)y);
+                         s, viewPi<VT>(d), d.n, d.gamma, (const double*)x, eta, (double*)y);
   }
 };
 
 template <typename VT, int G>
 struct RunResidual {
   static void run(Mdp& d, const double* V, double* r, hipStream_t s) {
-    hipLaunchKernelGGL((k_residual<VT, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
-                       viewPi<VT>(d), d.n, d.gamma, (const double*)d.cpi, V, r, red_ctx(d), d.st);
+    hipLaunchKernelGGL((k_policy_pass<VT, G, 0>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
+                       viewPi<VT>(d), d.n, d.gamma, (const double*)d.cpi, V, r, d.part);
   }
 };
 
 template <typename VT, int G>
 struct RunVi {
   static void run(Mdp& d, const double* Vin, double* Vout, hipStream_t s) {
-    hipLaunchKernelGGL((k_vi_sweep<VT, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
-                       viewPi<VT>(d), d.n, d.gamma, (const double*)d.cpi, Vin, Vout, red_ctx(d),
-                       d.st);
+    hipLaunchKernelGGL((k_policy_pass<VT, G, 1>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
+                       viewPi<VT>(d), d.n, d.gamma, (const double*)d.cpi, Vin, Vout, d.part);
   }
 };
 
@@ -357,7 +329,7 @@ struct RunGather {
   static void run(Mdp& d, const int32_t* pi, hipStream_t s) {
     hipLaunchKernelGGL((k_gather_policy<VT, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
                        viewP<VT>(d), viewPi<VT>(d), (const double*)d.cost, d.m, d.n, pi, d.cpi,
-                       red_ctx(d), d.st);
+                       d.part);
   }
 };
 
@@ -365,29 +337,41 @@ struct RunGather {
 
 void launch_bellman_sparse(Mdp& d, const double* V, double* TV, double* Phi, int32_t* pi,
                            const int32_t* pi_old, double tie_abs, bool compact, hipStream_t s) {
-  ProfScope p(d, KC_BELLMAN, s);
-  dispatch_vt_g<RunBellman>(d, d.G_bell, d, V, TV, Phi, pi, pi_old, tie_abs, compact, s);
+  {
+    ProfScope p(d, KC_BELLMAN, s);
+    dispatch_vt_g<RunBellman>(d, d.G_bell, d, V, TV, Phi, pi, pi_old, tie_abs, compact, s);
+  }
+  launch_finalize(d, FIN_BELLMAN, grid_for(d, d.G_bell), s);
 }
 
-void launch_japply_sparse(Mdp& d, bool fp32, const void* x, const double* eta, void* q_out,
-                          void* y, hipStream_t s) {
+void launch_japply_sparse(Mdp& d, bool fp32, const void* x, const double* eta, void* y,
+                          hipStream_t s) {
   ProfScope p(d, KC_JAPPLY, s);
-  dispatch_vt_g<RunJapply>(d, d.G_jap, d, fp32, x, eta, q_out, y, s);
+  dispatch_vt_g<RunJapply>(d, d.G_jap, d, fp32, x, eta, y, s);
 }
 
 void launch_residual_sparse(Mdp& d, const double* V, double* r, hipStream_t s) {
-  ProfScope p(d, KC_RESID, s);
-  dispatch_vt_g<RunResidual>(d, d.G_jap, d, V, r, s);
+  {
+    ProfScope p(d, KC_RESID, s);
+    dispatch_vt_g<RunResidual>(d, d.G_jap, d, V, r, s);
+  }
+  launch_finalize(d, FIN_RESID, grid_for(d, d.G_jap), s);
 }
 
 void launch_vi_sweep_sparse(Mdp& d, const double* Vin, double* Vout, hipStream_t s) {
-  ProfScope p(d, KC_VI, s);
-  dispatch_vt_g<RunVi>(d, d.G_jap, d, Vin, Vout, s);
+  {
+    ProfScope p(d, KC_VI, s);
+    dispatch_vt_g<RunVi>(d, d.G_jap, d, Vin, Vout, s);
+  }
+  launch_finalize(d, FIN_VI, grid_for(d, d.G_jap), s);
 }
 
 void launch_gather_policy_sparse(Mdp& d, const int32_t* pi, hipStream_t s) {
-  ProfScope p(d, KC_OTHER, s);
-  dispatch_vt_g<RunGather>(d, d.G_jap, d, pi, s);
+  {
+    ProfScope p(d, KC_OTHER, s);
+    dispatch_vt_g<RunGather>(d, d.G_jap, d, pi, s);
+  }
+  launch_finalize(d, FIN_GATHER, grid_for(d, d.G_jap), s);
 }
 
 }  // namespace ig

@@ -20,8 +20,6 @@ ig_status fail(ig_status s, const std::string& msg) {
   return s;
 }
 
-RedCtx red_ctx(Mdp& d) { return RedCtx{d.part, d.ticket}; }
-
 ig_status sync_status(Mdp& d, hipStream_t s) {
   IG_HIP(hipMemcpyAsync(d.hst, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   IG_HIP(hipStreamSynchronize(s));
@@ -107,7 +105,7 @@ void free_all(Mdp* d) {
     if (p) (void)hipFree(p);
   };
   F(d->col); F(d->val); F(d->off); F(d->width); F(d->offp); F(d->pcol); F(d->pval);
-  F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->ticket); F(d->pctl);
+  F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->pctl);
   F(d->ws.Q); F(d->ws.wA); F(d->ws.wB); F(d->ws.Vb); F(d->ws.r); F(d->ws.t); F(d->ws.pi);
   if (d->hst) (void)hipHostFree(d->hst);
   if (d->hpctl) (void)hipHostFree(d->hpctl);
@@ -140,6 +138,14 @@ std::vector<T> to_host(const T* p, size_t count, bool on_device, ig_status* st) 
 }
 
 }  // namespace
+
+// partial rows: kMaxBlocks * 8 for streaming kernels, one kPartStride row per
+// block of the Gram-Schmidt kernels, two sets of 256 rows for the persistent
+// engine
+size_t part_doubles(int64_t) {
+  return (size_t)std::max<int64_t>({(int64_t)kMaxBlocks * 8, (int64_t)2 * 256 * 72,
+                                    (int64_t)kGsBlocks * kPartStride});
+}
 
 ig_status ensure_workspace(Mdp& d, int W, bool fp32) {
   Workspace& w = d.ws;
@@ -360,13 +366,12 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
 
   if (dmalloc(&d->cost, (size_t)R * 8) || dmalloc(&d->cpi, (size_t)n * 8) ||
       dmalloc(&d->st, sizeof(DevStatus)) || dmalloc(&d->gs, sizeof(GivensState)) ||
-      dmalloc(&d->part, (size_t)kGsBlocks * (kMaxW + 1) * 8 + (size_t)kMaxBlocks * 8 * 8) ||
-      dmalloc(&d->ticket, 64) || dmalloc(&d->pctl, sizeof(PCtl)))
+      dmalloc(&d->part, part_doubles(d->n) * 8) ||
+      dmalloc(&d->pctl, sizeof(PCtl)))
     return IG_E_NOMEM;
   IG_HIP(hipMemcpy(d->cost, cost_t.data(), (size_t)R * 8, hipMemcpyHostToDevice));
   IG_HIP(hipMemset(d->st, 0, sizeof(DevStatus)));
   IG_HIP(hipMemset(d->gs, 0, sizeof(GivensState)));
-  IG_HIP(hipMemset(d->ticket, 0, 64));
   if (hipHostMalloc((void**)&d->hst, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&d->hpctl, sizeof(PCtl), hipHostMallocDefault) != hipSuccess)
     return fail(IG_E_NOMEM, "hipHostMalloc failed");

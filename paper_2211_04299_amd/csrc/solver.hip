@@ -24,12 +24,12 @@ void k_bellman(Mdp& d, const double* V, double* TV, double* Phi, int32_t* pi,
   else
     launch_bellman_dense(d, V, TV, Phi, pi, pi_old, tie, s);
 }
-void k_japply(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* eta,
-              void* q_out, void* y, hipStream_t s) {
+void k_japply(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* eta, void* y,
+              hipStream_t s) {
   if (d.fmt == IG_FMT_CSR)
-    launch_japply_sparse(d, fp32, x, eta, q_out, y, s);
+    launch_japply_sparse(d, fp32, x, eta, y, s);
   else
-    launch_japply_dense(d, fp32, pi, x, eta, q_out, y, s);
+    launch_japply_dense(d, fp32, pi, x, eta, y, s);
 }
 void k_residual(Mdp& d, const int32_t* pi, const double* V, double* r, hipStream_t s) {
   if (d.fmt == IG_FMT_CSR)
@@ -56,13 +56,12 @@ struct Bytes {
   double entry() const { return d.vb + (d.fmt == IG_FMT_CSR ? 4.0 : 0.0); }
   double nnz_pi() const { return (double)d.nnz / d.m; }
   double bellman() const { return d.nnz * entry() + d.n * (double)d.m * 8 + d.n * (8.0 + 8 + 4); }
-  double japply(bool fp32, bool qout) const {
+  double japply(bool fp32) const { return nnz_pi() * entry() + d.n * (fp32 ? 4.0 : 8.0) * 2; }
+  // form Q_c (reads c basis columns and w1, writes Q_c), two dot passes over
+  // c+1 columns, the axpy over c+1 columns (reads y, writes w1)
+  double gs(bool fp32, int c) const {
     const double xb = fp32 ? 4 : 8;
-    return nnz_pi() * entry() + d.n * xb * (qout ? 3 : 2);
-  }
-  double gs(bool fp32, int i) const {
-    const double xb = fp32 ? 4 : 8;
-    return d.n * xb * ((i + 1) + (2.0 * i + 2) + (i + 2));
+    return d.n * xb * ((c + 2.0) + (c + 2.0) + (c + 3.0) + (c + 2.0));
   }
   double update(bool fp32, int i) const { return d.n * (i * (fp32 ? 4.0 : 8.0) + 16); }
   double residual() const { return nnz_pi() * entry() + d.n * 24.0; }
@@ -79,6 +78,11 @@ struct Inner {
 // place.  On entry V = x0 and d.ws.r holds g - J x0 with infinity-norm r_inf
 // and squared 2-norm r_l2sq (host copy) / *r_l2sq_dev (device copy).
 // Stops when ||g - J V||_inf <= thr.
+//
+// Column c's Arnoldi step is y = J w1 / eta (w1 the previous once-orthogonal
+// vector), then two Gram-Schmidt passes and the Givens update; the residual
+// of column c-1's iterate, ||Q z||_inf, arrives with the step of column c.
+// A stop is always confirmed on the true FP64 residual g - J V.
 ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double r_l2sq,
                       const double* r_l2sq_dev, double thr, int W, int max_inner, bool fp32,
                       hipStream_t s, Inner& out) {
@@ -89,72 +93,67 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
     out.met = true;
     return IG_OK;
   }
-  const size_t xb = fp32 ? 4 : 8;
-  const double sqrt_n = std::sqrt((double)d.n);
+  const double xb = fp32 ? 4 : 8;
   double cycle_beta = std::sqrt(r_l2sq);
   IG_HIP(hipMemcpyAsync(ws.Vb, V, (size_t)d.n * 8, hipMemcpyDeviceToDevice, s));
   launch_form_q0(d, fp32, ws.r, r_l2sq_dev, s);
   out.bytes += d.n * (8.0 + xb + 16);
-  int i = 1;  // basis vectors Q_0..Q_{i-1} in this cycle
-  void* wcur = ws.wA;
-  void* wprev = ws.wB;
-  char* Q = (char*)ws.Q;
+  void* y = ws.wA;   // J times the newest basis vector
+  void* w1 = ws.wB;  // once-orthogonalised Arnoldi vector
   const double* eta_dev = &d.st->eta;
 
-  auto explicit_residual = [&]() -> ig_status {
-    launch_update(d, fp32, i, ws.Vb, V, s);
+  // V = Vb + Q_{0..cnt-1} y and its true residual (FP64)
+  auto explicit_residual = [&](int cnt) -> ig_status {
+    launch_update(d, fp32, cnt, ws.Vb, V, s);
     k_residual(d, pi, V, ws.r, s);
-    out.bytes += B.update(fp32, i) + B.residual();
+    out.bytes += B.update(fp32, cnt) + B.residual();
     ++out.expl;
     if (ig_status e = sync_status(d, s)) return e;
     out.res_inf = d.hst->res_inf;
     return IG_OK;
   };
 
-  for (;;) {
-    // q = J Q_{i-1}; the previous Arnoldi vector becomes Q_{i-1} = w / eta
-    if (i == 1)
-      k_japply(d, fp32, pi, Q, nullptr, nullptr, wcur, s);
-    else
-      k_japply(d, fp32, pi, wprev, eta_dev, Q + (size_t)(i - 1) * d.n * xb, wcur, s);
-    launch_arnoldi_orth(d, fp32, i, wcur, s);
-    out.bytes += B.japply(fp32, i > 1) + B.gs(fp32, i);
+  for (int c = 0;;) {
+    if (c == 0) {
+      k_japply(d, fp32, pi, ws.Q, nullptr, y, s);
+    } else {
+      k_japply(d, fp32, pi, w1, eta_dev, y, s);
+      launch_form_qi(d, fp32, c, w1, s);
+    }
+    launch_dots(d, fp32, c + 1, y, false, c > 0, s);
+    launch_axpy(d, fp32, c + 1, y, w1, s);
+    launch_dots(d, fp32, c + 1, w1, true, false, s);
+    out.bytes += B.japply(fp32) + B.gs(fp32, c);
     if (ig_status e = sync_status(d, s)) return e;
     ++out.steps;
     const double eta = d.hst->eta, rho = d.hst->rho;
-    if (!std::isfinite(eta) || !std::isfinite(rho))
+    if (!std::isfinite(eta) || !std::isfinite(rho) || (c > 0 && !std::isfinite(d.hst->res_impl)))
       return fail(IG_E_NUMERIC, "non-finite value in the Arnoldi process");
-    if (eta == 0.0) {  // ||q||_2 = 0: the least-squares solution is exact; leave the loop
-      ++out.breakdowns;
-      if (ig_status e = explicit_residual()) return e;
-      out.met = out.res_inf <= thr;
-      return IG_OK;
-    }
-    bool vcur = false;
-    // ||r||_inf <= ||r||_2 = rho <= sqrt(n) ||r||_inf: rho > sqrt(n) thr proves
-    // the rule unmet; otherwise evaluate the true residual.
-    if (!(rho > sqrt_n * thr)) {
-      if (ig_status e = explicit_residual()) return e;
-      vcur = true;
-      if (out.res_inf <= thr) {
+    // the test of Algorithm 2 for column c-1 (residual known one step late)
+    if (c > 0 && d.hst->res_impl <= thr) {
+      if (ig_status e = explicit_residual(c)) return e;
+      if (out.res_inf <= thr) {  // column c was speculative: not counted
+        --out.steps;
         out.met = true;
         return IG_OK;
       }
     }
-    if (out.steps >= max_inner) {
-      if (!vcur)
-        if (ig_status e = explicit_residual()) return e;
+    if (eta == 0.0) {  // ||q||_2 = 0: the least-squares solution is exact; leave the loop
+      ++out.breakdowns;
+      if (ig_status e = explicit_residual(c + 1)) return e;
       out.met = out.res_inf <= thr;
       return IG_OK;
     }
-    if (i == W) {  // restart from the residual at the current iterate
-      if (!vcur) {
-        if (ig_status e = explicit_residual()) return e;
-        if (out.res_inf <= thr) {
-          out.met = true;
-          return IG_OK;
-        }
+    // ||r||_inf <= ||r||_2 = rho: the rule holds for column c in exact arithmetic
+    if (rho <= thr || out.steps >= max_inner || c + 1 == W) {
+      if (ig_status e = explicit_residual(c + 1)) return e;
+      if (out.res_inf <= thr) {
+        out.met = true;
+        return IG_OK;
       }
+      if (out.steps >= max_inner) return IG_OK;
+    }
+    if (c + 1 == W) {  // restart from the residual at the current iterate
       const double nb = std::sqrt(d.hst->res_l2sq);
       if (nb > (1.0 - kStagnation) * cycle_beta) {
         out.stagnated = true;
@@ -165,11 +164,10 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
       IG_HIP(hipMemcpyAsync(ws.Vb, V, (size_t)d.n * 8, hipMemcpyDeviceToDevice, s));
       launch_form_q0(d, fp32, ws.r, &d.st->res_l2sq, s);
       out.bytes += d.n * (8.0 + xb + 16);
-      i = 1;
+      c = 0;
       continue;
     }
-    std::swap(wcur, wprev);
-    ++i;
+    ++c;
   }
 }
 

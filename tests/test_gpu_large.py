@@ -1,0 +1,71 @@
+"""Full-size mixed-precision workloads, checked by the FP64 oracle's Bellman
+operator on the returned V: the contraction certificate
+||V - V*||_inf <= ||T V - V||_inf / (1 - gamma) bounds the error against the
+exact optimum of the stored MDP without solving it, and the greedy policy of
+V must match the GPU's policy wherever the action gap is resolvable."""
+import numpy as np
+import pytest
+
+from oracle import mdp_oracle as O
+from paper_2211_04299_amd import synth
+
+from gpu_helpers import host, zeros
+
+pytestmark = pytest.mark.gpu
+
+
+def igm():
+    from paper_2211_04299_amd import igmres
+    return igmres
+
+
+def solve_certified(mdp, store, tol, restart, mode="mixed"):
+    I = igm()
+    if mdp.fmt == "csr":
+        stored = mdp.with_values(val=synth.round_values(mdp.val, store))
+        ref = mdp.with_values(val=synth.upcast_values(stored.val, store))
+    else:
+        stored = mdp.with_values(P=synth.round_values(mdp.P, store))
+        ref = mdp.with_values(P=synth.upcast_values(stored.P, store))
+    with I.mdp_create(stored, store=store) as h:
+        V = zeros(mdp.n)
+        pi = zeros(mdp.n, "int32")
+        st = h.igmres_pi_solve(V, pi, I.params_default(mdp.gamma, tol=tol, restart=restart, mode=mode))
+        Vh, pih = host(V), host(pi)
+    TV, pio, res = O.bellman(ref, Vh)
+    return Vh, pih, st, ref, TV, pio, res
+
+
+def check(mdp, Vh, pih, st, ref, TV, pio, res, tol):
+    assert st["converged"] == 1
+    # the FP64 residual the GPU used for its stop decision, recomputed on the CPU
+    assert res <= tol * (1 + 1e-6)
+    cert = res / (1 - mdp.gamma)
+    rel_bound = cert / np.max(np.abs(TV))
+    assert rel_bound <= 1e-6, rel_bound          # mixed-path tolerance
+    # greedy policy of the returned V, wherever the gap exceeds rounding
+    Q = O.q_values(ref, Vh)
+    Qs = np.sort(Q, axis=1)
+    gap = Qs[:, 1] - Qs[:, 0] if mdp.m > 1 else np.full(mdp.n, np.inf)
+    sel = gap > 1e-9
+    assert np.array_equal(pih[sel], pio[sel])
+    return rel_bound
+
+
+def test_c4_banded_fp32_full_size():
+    mdp = synth.config("c4", seed=0)
+    out = solve_certified(mdp, "fp32", tol=1e-8, restart=40)
+    rb = check(mdp, *out, tol=1e-8)
+    print(f"c4: outer={out[2]['outer']} inner={out[2]['inner']} time_ms={out[2]['time_ms']:.1f} "
+          f"rel_error_bound={rb:.2e}")
+
+
+@pytest.mark.parametrize("store", ["fp32", "bf16"])
+def test_c3_dense_full_size(store):
+    mdp = synth.config("c3", seed=0)
+    out = solve_certified(mdp, store, tol=1e-8, restart=30)
+    rb = check(mdp, *out, tol=1e-8)
+    # against the unrounded FP64 MDP: reported (BF16 rounding moves V* itself)
+    _, _, res64 = O.bellman(mdp, out[0])
+    print(f"c3 {store}: outer={out[2]['outer']} inner={out[2]['inner']} time_ms={out[2]['time_ms']:.1f} "
+          f"rel_error_bound(stored MDP)={rb:.2e} residual on the FP64 MDP={res64:.2e}")
