@@ -109,6 +109,10 @@ typedef struct {
                           persistent launch for the whole solve (sparse,
                           up to 256*32 slices of 64 states); auto picks 2
                           when it applies                                     */
+  int32_t blocks;      /* persistent engine: workgroups of the launch (0 =
+                          from the shape); clamped so that a workgroup owns
+                          1..32 slices.  The result depends on this count
+                          (reduction order), never on other device work.      */
 } ig_params;
 
 typedef struct {
@@ -127,6 +131,9 @@ typedef struct {
   double cert_bound;      /* res_inf / (1 - gamma) >= ||V - V*||_inf          */
   double time_ms;         /* device time of the call (HIP events)             */
   double alg_bytes;       /* algorithmic HBM bytes the call had to move       */
+  double latency_ms;      /* serving: submission to result ready (host clock);
+                             0 for the direct entry points                    */
+  double queue_ms;        /* serving: submission to launch                    */
 } ig_stats;
 
 typedef struct ig_mdp_s* ig_mdp_t;
@@ -134,7 +141,7 @@ typedef struct ig_mdp_s* ig_mdp_t;
 /* Fill `p` with defaults for discount gamma: alpha = (1-gamma)/(2(1+gamma))
  * (midpoint of Theorem 1's range), restart 30, max_outer 1000,
  * max_inner 100000, tol 1e-8, FP64 mode, opi_sweeps 20, forcing 0,
- * eval_rtol 1e-13, engine 0. */
+ * eval_rtol 1e-13, engine 0, blocks 0. */
 void ig_params_default(ig_params* p, double gamma);
 
 /* Copy P and g to the device in the GPU layout (sliced ELL, 64 states per
@@ -225,6 +232,82 @@ ig_status ig_profile_enable(ig_mdp_t mdp, unsigned mask);
  * reset (synchronises on the recorded events).  ms and launches have
  * IG_PROFILE_CLASSES entries (host memory). */
 ig_status ig_profile_read(ig_mdp_t mdp, double* ms, int64_t* launches, int reset);
+
+/* ---- Continuous-batching serving ------------------------------------------
+ * Many Algorithm 2 solves (igmres_pi_solve, persistent engine) in flight on
+ * one GPU.  A server reserves one device arena of hbm_budget bytes, `slots`
+ * HIP streams with pinned result buffers, `prep_threads` host threads that
+ * convert requests to the device layout, and one scheduling thread.
+ *   submit -> (prep thread) footprint; first-fit allocation in the arena, in
+ *   submission order, waiting while it does not fit -> conversion and
+ *   asynchronous upload -> (scheduler) launch of the request's persistent
+ *   solve on a free slot once the workgroups of all running solves, spread
+ *   over the 8 XCDs, stay co-resident -> completion -> results copied out,
+ *   arena space and slot returned.
+ * Admission and retirement happen while other solves run, so arriving
+ * requests join the work on the device as slots and memory free up.  A
+ * request's result depends only on the request (its workgroup count comes
+ * from its shape, params->blocks and cfg.block_slices; every reduction is
+ * per request): it is bitwise the same alone and in any mix.
+ * Requests are sparse (IG_FMT_CSR) with host arrays; the server BORROWS
+ * desc's arrays and V0 until srv_poll reports the ticket done (they are
+ * read by the preparation, which runs after srv_submit returns).
+ * The server's own calls are thread-safe. */
+typedef struct ig_server_s* ig_server_t;
+typedef struct {
+  int32_t device;
+  int32_t slots;          /* solves running at once, 1..16 (the device runs
+                             kernels of at most GPU_MAX_HW_QUEUES streams at
+                             once, 4 by default)                              */
+  int32_t prep_threads;   /* host conversion/upload threads, 1..16            */
+  int32_t block_slices;   /* params->blocks == 0: a solve gets
+                             ceil(slices / block_slices) workgroups           */
+  int64_t max_states;     /* largest n accepted (sizes pinned buffers)       */
+  size_t hbm_budget;      /* device bytes reserved for resident requests     */
+} ig_server_config;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int32_t queued, preparing, ready, running;
+  int32_t peak_running;   /* most solves seen running at once                */
+  int32_t xcd_units_cap;  /* co-residency budget (workgroups per XCD)        */
+  size_t arena_bytes, arena_used, arena_peak;
+} ig_server_info;
+
+/* slots 4, prep_threads 2, block_slices 16, max_states 2^19,
+ * hbm_budget 32 GiB, device 0. */
+void ig_server_config_default(ig_server_config* cfg);
+
+/* Reserve the arena and start the threads.  IG_E_INVALID (bad config),
+ * IG_E_NOMEM (arena or pinned buffers), IG_E_DEVICE. */
+ig_status srv_create(const ig_server_config* cfg, ig_server_t* out);
+
+/* Queue one igmres_pi_solve request and return at once with its ticket.
+ * desc: host CSR MDP (validated if desc->validate); V0: host n doubles or
+ * NULL for V0 = 0; params: mode, restart <= 64, tol, ... as for
+ * igmres_pi_solve (engine is ignored: the persistent engine is used).
+ * IG_E_INVALID for a malformed request (checked here: shape, pointers,
+ * params; the MDP data itself is checked by the preparation and reported by
+ * srv_result), IG_E_TOO_LARGE if n > max_states or restart > 64. */
+ig_status srv_submit(ig_server_t srv, const ig_mdp_desc* desc, const double* V0,
+                     const ig_params* params, uint64_t* ticket);
+
+/* *done = 1 once the ticket's result is ready (or failed), else 0.
+ * IG_E_INVALID for an unknown ticket. */
+ig_status srv_poll(ig_server_t srv, uint64_t ticket, int32_t* done);
+
+/* Wait for the ticket, copy V (n doubles) and pi (n int32) to HOST memory
+ * (either may be NULL), fill stats (may be NULL), and release the ticket.
+ * Returns the request's status: IG_OK, IG_E_NOCONV (V, pi = last iterate),
+ * IG_E_INVALID / IG_E_TOO_LARGE (found by the preparation, e.g. a footprint
+ * above hbm_budget), IG_E_NUMERIC, IG_E_DEVICE. */
+ig_status srv_result(ig_server_t srv, uint64_t ticket, double* V, int32_t* pi, ig_stats* stats);
+
+ig_status srv_get_info(ig_server_t srv, ig_server_info* info);
+
+/* Finish every submitted request, stop the threads and free everything
+ * (results not collected are dropped).  NULL is ignored. */
+void srv_destroy(ig_server_t srv);
 
 /* Thread-local description of the last error (never NULL). */
 const char* ig_last_error(void);

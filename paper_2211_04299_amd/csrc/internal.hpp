@@ -2,6 +2,7 @@
 // kernel launchers (one .hip file per kernel family).
 #pragma once
 
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -37,8 +38,19 @@ struct Workspace {
   int32_t* pi = nullptr;  // internal policy buffer
 };
 
+// Bump allocation inside a caller-owned device region (serving): handles
+// created in a region never call hipMalloc/hipFree and upload on `stream`.
+struct DevRegion {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+};
+
 struct Mdp {
   int device = 0;
+  DevRegion* region = nullptr;          // non-null: allocate from the region
+  hipStream_t stream = nullptr;         // stream of the region-mode uploads
+  std::vector<std::shared_ptr<void>> keep;  // host staging alive until uploads finish
+  bool own_host_mirrors = true;         // hst / hpctl allocated by the handle
   int64_t n = 0;
   int m = 0;
   double gamma = 0;
@@ -134,7 +146,18 @@ void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s);
 ig_status persistent_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& st,
                             hipStream_t s);
 bool persistent_fits(const Mdp& d);
-int persistent_grid(const Mdp& d);
+int persistent_grid(const Mdp& d, int requested = 0);
+// asynchronous form for serving: enqueue the solve on `s` (V already holds
+// V0), then the copy of the control block into d.hpctl; collect after the
+// stream has passed that point.
+ig_status persistent_launch(Mdp& d, double* V, int32_t* pi, const ig_params& p, hipStream_t s);
+ig_status persistent_collect(Mdp& d, ig_stats& st);
+// device bytes mdp_create + ensure_workspace(restart, mode) would allocate
+ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size_t* bytes);
+ig_status create_in(const ig_mdp_desc* desc, Mdp* d);
+ig_status region_alloc(Mdp& d, size_t bytes, void** p);
+void release_handle(Mdp* d);
+inline size_t round_alloc(size_t b) { return ((b < 8 ? 8 : b) + 255) & ~(size_t)255; }
 
 // ---- Krylov (Gram-Schmidt, Givens, update) -------------------------------
 // reduce the partials of the last nb-block finishing kernel into status /

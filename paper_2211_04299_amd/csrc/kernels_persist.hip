@@ -603,18 +603,30 @@ leave:
 }
 
 template <typename VT, typename XT, int G>
-ig_status launch_persist(Mdp& d, const PArgs<VT, XT>& a, int nblocks, hipStream_t s) {
+ig_status launch_persist(Mdp& d, const PArgs<VT, XT>& a, int nblocks, bool coop, hipStream_t s) {
   void* args[] = {(void*)&a};
   ProfScope prof(d, KC_PERSIST, s);
-  IG_HIP(hipLaunchCooperativeKernel((const void*)k_persist<VT, XT, G>, dim3(nblocks), dim3(kPB),
-                                    args, 0, s));
+  // A plain launch is used by the serving loop, which keeps every block of
+  // all running solves co-resident by admission (cooperative launches are
+  // serialised by the runtime).
+  if (coop)
+    IG_HIP(hipLaunchCooperativeKernel((const void*)k_persist<VT, XT, G>, dim3(nblocks), dim3(kPB),
+                                      args, 0, s));
+  else
+    IG_HIP(hipLaunchKernel((const void*)k_persist<VT, XT, G>, dim3(nblocks), dim3(kPB), args, 0, s));
   return IG_OK;
 }
 
-int persistent_blocks(const Mdp& d, int* spb_out) {
-  int want = (int)std::max<int64_t>(1, std::min<int64_t>(d.nslices, d.nslices / 4));
-  if (const char* e = std::getenv("IG_PERSIST_BLOCKS")) want = std::max(1, std::atoi(e));
-  if (want >= 16) want = want / 8 * 8;  // whole XCD groups
+// Blocks of one solve: `requested` > 0 asks for that many (clamped so that
+// a block owns at most kPMaxSpb slices); otherwise a quarter of the slices,
+// in whole XCD groups.  Depends only on the shape, the request and the CU
+// count, never on other work on the device.
+int persistent_blocks(const Mdp& d, int* spb_out, int requested = 0) {
+  int want = requested > 0 ? requested
+                           : (int)std::max<int64_t>(1, std::min<int64_t>(d.nslices, d.nslices / 4));
+  if (requested <= 0)
+    if (const char* e = std::getenv("IG_PERSIST_BLOCKS")) want = std::max(1, std::atoi(e));
+  if (requested <= 0 && want >= 16) want = want / 8 * 8;  // whole XCD groups
   const int cap = std::min(kPMaxBlocks, std::max(1, d.num_cu));
   int nb = (int)std::min<int64_t>(std::min<int64_t>(d.nslices, cap), want);
   nb = std::max(nb, (int)((d.nslices + kPMaxSpb - 1) / kPMaxSpb));
@@ -626,9 +638,9 @@ int persistent_blocks(const Mdp& d, int* spb_out) {
 }
 
 template <typename VT, typename XT>
-ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, hipStream_t s) {
+ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coop, hipStream_t s) {
   int spb = 0;
-  const int nb = persistent_blocks(d, &spb);
+  const int nb = persistent_blocks(d, &spb, p.blocks);
   PArgs<VT, XT> a;
   a.P = SellP<VT>{d.col, (const VT*)d.val, d.off, d.width};
   a.Pp = SellPi<VT>{d.pcol, (VT*)d.pval, d.offp, d.width};
@@ -665,50 +677,59 @@ ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, hipStrea
   const int per_state = kPB / (kSlice * spb);
   const int G = per_state >= 16 ? 16 : per_state >= 8 ? 8 : per_state >= 4 ? 4 : per_state >= 2 ? 2 : 1;
   switch (G) {
-    case 16: return launch_persist<VT, XT, 16>(d, a, nb, s);
-    case 8: return launch_persist<VT, XT, 8>(d, a, nb, s);
-    case 4: return launch_persist<VT, XT, 4>(d, a, nb, s);
-    case 2: return launch_persist<VT, XT, 2>(d, a, nb, s);
-    default: return launch_persist<VT, XT, 1>(d, a, nb, s);
+    case 16: return launch_persist<VT, XT, 16>(d, a, nb, coop, s);
+    case 8: return launch_persist<VT, XT, 8>(d, a, nb, coop, s);
+    case 4: return launch_persist<VT, XT, 4>(d, a, nb, coop, s);
+    case 2: return launch_persist<VT, XT, 2>(d, a, nb, coop, s);
+    default: return launch_persist<VT, XT, 1>(d, a, nb, coop, s);
   }
 }
 
 }  // namespace
 
-int persistent_grid(const Mdp& d) {
+int persistent_grid(const Mdp& d, int requested) {
   int spb = 0;
-  return persistent_blocks(d, &spb);
+  return persistent_blocks(d, &spb, requested);
 }
 
 bool persistent_fits(const Mdp& d) {
-  if (d.fmt != IG_FMT_CSR || !d.coop || d.num_cu <= 0) return false;
+  if (d.fmt != IG_FMT_CSR || d.num_cu <= 0) return false;
   int spb = 0;
   persistent_blocks(d, &spb);
   return spb <= kPMaxSpb && d.n >= 1;
 }
 
-ig_status persistent_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& st,
-                            hipStream_t s) {
+namespace {
+
+ig_status launch_impl(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coop, hipStream_t s) {
   if (!persistent_fits(d)) return fail(IG_E_TOO_LARGE, "shape does not fit the persistent engine");
   if (p.restart > kPMaxW) return fail(IG_E_TOO_LARGE, "the persistent engine takes restart <= 64");
+  if (coop && !d.coop) return fail(IG_E_DEVICE, "device does not support cooperative launches");
   const bool fp32 = p.mode == IG_MODE_MIXED;
   if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
   IG_HIP(hipMemsetAsync(d.pctl, 0, sizeof(PCtl), s));
-  ig_status e;
   switch (d.store) {
     case IG_FP64:
-      e = fp32 ? run_typed<double, float>(d, V, pi, p, s) : run_typed<double, double>(d, V, pi, p, s);
-      break;
+      return fp32 ? run_typed<double, float>(d, V, pi, p, coop, s)
+                  : run_typed<double, double>(d, V, pi, p, coop, s);
     case IG_FP32:
-      e = fp32 ? run_typed<float, float>(d, V, pi, p, s) : run_typed<float, double>(d, V, pi, p, s);
-      break;
+      return fp32 ? run_typed<float, float>(d, V, pi, p, coop, s)
+                  : run_typed<float, double>(d, V, pi, p, coop, s);
     default:
-      e = fp32 ? run_typed<bf16, float>(d, V, pi, p, s) : run_typed<bf16, double>(d, V, pi, p, s);
-      break;
+      return fp32 ? run_typed<bf16, float>(d, V, pi, p, coop, s)
+                  : run_typed<bf16, double>(d, V, pi, p, coop, s);
   }
-  if (e) return e;
+}
+
+}  // namespace
+
+ig_status persistent_launch(Mdp& d, double* V, int32_t* pi, const ig_params& p, hipStream_t s) {
+  if (ig_status e = launch_impl(d, V, pi, p, false, s)) return e;
   IG_HIP(hipMemcpyAsync(d.hpctl, d.pctl, sizeof(PCtl), hipMemcpyDeviceToHost, s));
-  IG_HIP(hipStreamSynchronize(s));
+  return IG_OK;
+}
+
+ig_status persistent_collect(Mdp& d, ig_stats& st) {
   const PCtl& c = *d.hpctl;
   st.outer = c.outer;
   st.inner = c.inner;
@@ -724,6 +745,14 @@ ig_status persistent_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, 
   if (c.nonfinite) return fail(IG_E_NUMERIC, "NaN or Inf during the solve");
   if (!c.converged) return fail(IG_E_NOCONV, "max_outer reached");
   return IG_OK;
+}
+
+ig_status persistent_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& st,
+                            hipStream_t s) {
+  if (ig_status e = launch_impl(d, V, pi, p, true, s)) return e;
+  IG_HIP(hipMemcpyAsync(d.hpctl, d.pctl, sizeof(PCtl), hipMemcpyDeviceToHost, s));
+  IG_HIP(hipStreamSynchronize(s));
+  return persistent_collect(d, st);
 }
 
 }  // namespace ig

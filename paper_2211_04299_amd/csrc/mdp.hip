@@ -89,9 +89,22 @@ inline double store_val(void* dst, int64_t pos, ig_dtype st, double x) {
   }
 }
 
+inline size_t round256(size_t b) { return round_alloc(b); }
+
+// the region of the handle being created (set by create_impl / ensure_workspace)
+thread_local DevRegion* t_region = nullptr;
+
 template <typename T>
 ig_status dmalloc(T** p, size_t bytes) {
   *p = nullptr;
+  if (t_region) {
+    const size_t b = round256(bytes);
+    if (t_region->used + b > t_region->size)
+      return fail(IG_E_TOO_LARGE, "device region too small for the MDP");
+    *p = (T*)(t_region->base + t_region->used);
+    t_region->used += b;
+    return IG_OK;
+  }
   if (bytes == 0) bytes = 8;
   if (hipMalloc((void**)p, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -100,15 +113,41 @@ ig_status dmalloc(T** p, size_t bytes) {
   return IG_OK;
 }
 
+// host -> device copy; in region mode asynchronous on the handle's stream
+// with the host buffer kept alive by the handle
+template <typename V>
+ig_status upload(Mdp* d, void* dst, V&& vec) {
+  const size_t bytes = vec.size() * sizeof(typename std::decay_t<V>::value_type);
+  if (bytes == 0) return IG_OK;
+  if (d->region) {
+    auto holder = std::make_shared<std::decay_t<V>>(std::move(vec));
+    if (hipMemcpyAsync(dst, holder->data(), bytes, hipMemcpyHostToDevice, d->stream) != hipSuccess)
+      return fail(IG_E_DEVICE, "hipMemcpyAsync upload failed");
+    d->keep.push_back(holder);
+    return IG_OK;
+  }
+  if (hipMemcpy(dst, vec.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(IG_E_DEVICE, "hipMemcpy upload failed");
+  return IG_OK;
+}
+
+ig_status dzero(Mdp* d, void* dst, size_t bytes) {
+  const hipError_t e = d->region ? hipMemsetAsync(dst, 0, bytes, d->stream) : hipMemset(dst, 0, bytes);
+  return e == hipSuccess ? IG_OK : fail(IG_E_DEVICE, "hipMemset failed");
+}
+
 void free_all(Mdp* d) {
-  auto F = [](void* p) {
-    if (p) (void)hipFree(p);
+  const bool dev = d->region == nullptr;
+  auto F = [dev](void* p) {
+    if (p && dev) (void)hipFree(p);
   };
   F(d->col); F(d->val); F(d->off); F(d->width); F(d->offp); F(d->pcol); F(d->pval);
   F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->pctl);
   F(d->ws.Q); F(d->ws.wA); F(d->ws.wB); F(d->ws.Vb); F(d->ws.r); F(d->ws.t); F(d->ws.pi);
-  if (d->hst) (void)hipHostFree(d->hst);
-  if (d->hpctl) (void)hipHostFree(d->hpctl);
+  if (d->own_host_mirrors) {
+    if (d->hst) (void)hipHostFree(d->hst);
+    if (d->hpctl) (void)hipHostFree(d->hpctl);
+  }
   if (d->ev0) (void)hipEventDestroy(d->ev0);
   if (d->ev1) (void)hipEventDestroy(d->ev1);
   for (auto& pool : d->prof_ev)
@@ -148,6 +187,11 @@ size_t part_doubles(int64_t) {
 }
 
 ig_status ensure_workspace(Mdp& d, int W, bool fp32) {
+  struct RegionScope {
+    DevRegion* prev;
+    explicit RegionScope(DevRegion* r) : prev(t_region) { t_region = r; }
+    ~RegionScope() { t_region = prev; }
+  } scope(d.region);
   Workspace& w = d.ws;
   const size_t n = (size_t)d.n;
   if (!w.Vb) {
@@ -156,6 +200,7 @@ ig_status ensure_workspace(Mdp& d, int W, bool fp32) {
       return IG_E_NOMEM;
   }
   if (w.Q && w.W >= W && w.fp32 == fp32) return IG_OK;
+  if (d.region && w.Q) return fail(IG_E_TOO_LARGE, "workspace of a region handle cannot grow");
   if (w.Q) (void)hipFree(w.Q);
   if (w.wA) (void)hipFree(w.wA);
   if (w.wB) (void)hipFree(w.wB);
@@ -168,6 +213,7 @@ ig_status ensure_workspace(Mdp& d, int W, bool fp32) {
   w.fp32 = fp32;
   return IG_OK;
 }
+
 
 static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d) {
   if (!desc) return fail(IG_E_INVALID, "desc is NULL");
@@ -314,13 +360,13 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         dmalloc(&d->width, (size_t)ns * 4) || dmalloc(&d->pcol, (size_t)totp * 4) ||
         dmalloc(&d->pval, (size_t)totp * d->vb))
       return IG_E_NOMEM;
-    IG_HIP(hipMemcpy(d->col, scol.data(), (size_t)tot * 4, hipMemcpyHostToDevice));
-    IG_HIP(hipMemcpy(d->val, sval.data(), (size_t)tot * d->vb, hipMemcpyHostToDevice));
-    IG_HIP(hipMemcpy(d->off, off.data(), (size_t)ns * 8, hipMemcpyHostToDevice));
-    IG_HIP(hipMemcpy(d->offp, offp.data(), (size_t)ns * 8, hipMemcpyHostToDevice));
-    IG_HIP(hipMemcpy(d->width, width.data(), (size_t)ns * 4, hipMemcpyHostToDevice));
-    IG_HIP(hipMemset(d->pcol, 0, (size_t)totp * 4));
-    IG_HIP(hipMemset(d->pval, 0, (size_t)totp * d->vb));
+    if (ig_status e = upload(d, d->col, std::move(scol))) return e;
+    if (ig_status e = upload(d, d->val, std::move(sval))) return e;
+    if (ig_status e = upload(d, d->off, std::move(off))) return e;
+    if (ig_status e = upload(d, d->offp, std::move(offp))) return e;
+    if (ig_status e = upload(d, d->width, std::vector<int32_t>(width))) return e;
+    if (ig_status e = dzero(d, d->pcol, (size_t)totp * 4)) return e;
+    if (ig_status e = dzero(d, d->pval, (size_t)totp * d->vb)) return e;
 
     // lanes per state: enough lanes in flight to cover latency on 256 CUs
     const int64_t target = (int64_t)1 << 18;
@@ -361,7 +407,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     d->stored = total;
     d->maxK = (int)n;
     if (dmalloc(&d->P, (size_t)total * d->vb)) return IG_E_NOMEM;
-    IG_HIP(hipMemcpy(d->P, sval.data(), (size_t)total * d->vb, hipMemcpyHostToDevice));
+    if (ig_status e = upload(d, d->P, std::move(sval))) return e;
   }
 
   if (dmalloc(&d->cost, (size_t)R * 8) || dmalloc(&d->cpi, (size_t)n * 8) ||
@@ -369,14 +415,15 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       dmalloc(&d->part, part_doubles(d->n) * 8) ||
       dmalloc(&d->pctl, sizeof(PCtl)))
     return IG_E_NOMEM;
-  IG_HIP(hipMemcpy(d->cost, cost_t.data(), (size_t)R * 8, hipMemcpyHostToDevice));
-  IG_HIP(hipMemset(d->st, 0, sizeof(DevStatus)));
-  IG_HIP(hipMemset(d->gs, 0, sizeof(GivensState)));
-  if (hipHostMalloc((void**)&d->hst, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&d->hpctl, sizeof(PCtl), hipHostMallocDefault) != hipSuccess)
+  if (ig_status e = upload(d, d->cost, std::move(cost_t))) return e;
+  if (ig_status e = dzero(d, d->st, sizeof(DevStatus))) return e;
+  if (ig_status e = dzero(d, d->gs, sizeof(GivensState))) return e;
+  if (d->own_host_mirrors &&
+      (hipHostMalloc((void**)&d->hst, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess ||
+       hipHostMalloc((void**)&d->hpctl, sizeof(PCtl), hipHostMallocDefault) != hipSuccess))
     return fail(IG_E_NOMEM, "hipHostMalloc failed");
-  IG_HIP(hipMemset(d->pctl, 0, sizeof(PCtl)));
-  std::memset(d->hst, 0, sizeof(DevStatus));
+  if (ig_status e = dzero(d, d->pctl, sizeof(PCtl))) return e;
+  if (d->hst) std::memset(d->hst, 0, sizeof(DevStatus));
   IG_HIP(hipEventCreate(&d->ev0));
   IG_HIP(hipEventCreate(&d->ev1));
   IG_HIP(hipGetDevice(&d->device));
@@ -384,8 +431,73 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
   IG_HIP(hipDeviceGetAttribute(&d->num_cu, hipDeviceAttributeMultiprocessorCount, d->device));
   IG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, d->device));
   d->coop = coop != 0;
-  IG_HIP(hipDeviceSynchronize());
+  if (!d->region) IG_HIP(hipDeviceSynchronize());
   (void)stream;
+  return IG_OK;
+}
+
+// create_impl with the handle's region (if any) as the allocation target
+ig_status create_in(const ig_mdp_desc* desc, Mdp* d) {
+  struct RegionScope {
+    DevRegion* prev;
+    explicit RegionScope(DevRegion* r) : prev(t_region) { t_region = r; }
+    ~RegionScope() { t_region = prev; }
+  } scope(d->region);
+  try {
+    return create_impl(desc, d->stream, d);
+  } catch (const std::bad_alloc&) {
+    return fail(IG_E_NOMEM, "host allocation failed while converting the MDP");
+  }
+}
+
+// release what a handle holds (no device synchronisation; region handles
+// return nothing to the allocator, their region is the owner's)
+void release_handle(Mdp* d) { free_all(d); }
+
+// one more allocation from a region handle's region
+ig_status region_alloc(Mdp& d, size_t bytes, void** p) {
+  if (!d.region) return fail(IG_E_INVALID, "handle has no region");
+  struct RegionScope {
+    DevRegion* prev;
+    explicit RegionScope(DevRegion* r) : prev(t_region) { t_region = r; }
+    ~RegionScope() { t_region = prev; }
+  } scope(d.region);
+  char* q = nullptr;
+  if (ig_status e = dmalloc(&q, bytes)) return e;
+  *p = q;
+  return IG_OK;
+}
+
+// Device bytes that create_in + ensure_workspace(restart, fp32) allocate,
+// each allocation rounded to 256 bytes.
+ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size_t* bytes) {
+  if (!desc || !bytes || desc->n < 1 || desc->m < 1) return fail(IG_E_INVALID, "bad description");
+  const int64_t n = desc->n, R = n * (int64_t)desc->m;
+  const size_t vb = dtype_bytes(desc->store);
+  size_t b = 0;
+  if (desc->fmt == IG_FMT_CSR) {
+    if (desc->inputs_on_device) return fail(IG_E_INVALID, "footprint needs host CSR arrays");
+    const int64_t* rp = desc->row_ptr;
+    const int64_t ns = (n + kSlice - 1) / kSlice;
+    int64_t tot = 0, totp = 0;
+    for (int64_t sl = 0; sl < ns; ++sl) {
+      int64_t w = 0;
+      for (int64_t s = sl * kSlice; s < std::min(n, (sl + 1) * kSlice); ++s)
+        for (int a = 0; a < desc->m; ++a) w = std::max(w, rp[s * desc->m + a + 1] - rp[s * desc->m + a]);
+      tot += (int64_t)desc->m * w * kSlice;
+      totp += w * kSlice;
+    }
+    b += round256(tot * 4) + round256(tot * vb) + 2 * round256(ns * 8) + round256(ns * 4) +
+         round256(totp * 4) + round256(totp * vb);
+  } else {
+    b += round256((size_t)R * n * vb);
+  }
+  b += round256(R * 8) + round256(n * 8) + round256(sizeof(DevStatus)) +
+       round256(sizeof(GivensState)) + round256(part_doubles(n) * 8) + round256(sizeof(PCtl));
+  const size_t xb = fp32 ? 4 : 8;
+  b += 3 * round256(n * 8) + round256(n * 4);                             // Vb, r, t, pi
+  b += round256((size_t)(restart + 1) * n * xb) + 2 * round256(n * xb);  // Q, wA, wB
+  *bytes = b;
   return IG_OK;
 }
 
@@ -411,6 +523,7 @@ void ig_params_default(ig_params* p, double gamma) {
   p->forcing = 0;
   p->eval_rtol = 1e-13;
   p->engine = 0;
+  p->blocks = 0;
 }
 
 ig_status mdp_create(const ig_mdp_desc* desc, void* stream, ig_mdp_t* out) {
@@ -457,7 +570,7 @@ ig_status mdp_get_info(ig_mdp_t mdp, ig_mdp_info* info) {
   info->store = d.store;
   info->fmt = d.fmt;
   info->gamma = d.gamma;
-  info->persistent_ok = ig::persistent_fits(d) ? 1 : 0;
+  info->persistent_ok = (d.coop && ig::persistent_fits(d)) ? 1 : 0;
   info->persistent_blocks = info->persistent_ok ? ig::persistent_grid(d) : 0;
   return IG_OK;
 }

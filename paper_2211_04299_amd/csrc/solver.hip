@@ -179,6 +179,7 @@ ig_status check_params(const Mdp& d, const ig_params* p, bool need_alpha) {
   if (p->max_outer < 1 || p->max_inner < 1) return fail(IG_E_INVALID, "iteration caps must be >= 1");
   if (!(p->tol > 0.0)) return fail(IG_E_INVALID, "tol must be > 0");
   if (p->mode != IG_MODE_FP64 && p->mode != IG_MODE_MIXED) return fail(IG_E_INVALID, "bad mode");
+  if (p->blocks < 0) return fail(IG_E_INVALID, "blocks must be >= 0");
   (void)d;
   return IG_OK;
 }
@@ -220,7 +221,7 @@ ig_status run_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stat
                      hipStream_t s) {
   const bool fp32 = p.mode == IG_MODE_MIXED;
   if (p.engine < 0 || p.engine > 2) return fail(IG_E_INVALID, "engine must be 0, 1 or 2");
-  if (p.engine == 2 || (p.engine == 0 && persistent_fits(d)))
+  if (p.engine == 2 || (p.engine == 0 && d.coop && persistent_fits(d)))
     return persistent_igmres(d, V, pi, p, st, s);
   if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
   for (int k = 0;; ++k) {

@@ -36,7 +36,8 @@ PROFILE_CLASS_NAMES = ["bellman", "japply", "gram_schmidt", "update", "residual"
 
 EXPORTS = ["ig_params_default", "mdp_create", "mdp_destroy", "mdp_get_info", "bellman_apply",
            "policy_eval_gmres", "igmres_pi_solve", "pi_solve", "opi_solve", "ipi_vi_solve",
-           "ig_profile_enable", "ig_profile_read", "ig_last_error"]
+           "ig_profile_enable", "ig_profile_read", "ig_last_error", "ig_server_config_default",
+           "srv_create", "srv_submit", "srv_poll", "srv_result", "srv_get_info", "srv_destroy"]
 
 
 class MdpDesc(C.Structure):
@@ -50,7 +51,7 @@ class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("restart", C.c_int32), ("max_outer", C.c_int32),
                 ("max_inner", C.c_int32), ("tol", C.c_double), ("mode", C.c_int),
                 ("opi_sweeps", C.c_int32), ("forcing", C.c_int32), ("eval_rtol", C.c_double),
-                ("engine", C.c_int32)]
+                ("engine", C.c_int32), ("blocks", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -58,7 +59,7 @@ class Stats(C.Structure):
                 ("bellman_passes", C.c_int32), ("explicit_residuals", C.c_int32),
                 ("breakdowns", C.c_int32), ("stagnations", C.c_int32), ("converged", C.c_int32),
                 ("res_inf", C.c_double), ("cert_bound", C.c_double), ("time_ms", C.c_double),
-                ("alg_bytes", C.c_double)]
+                ("alg_bytes", C.c_double), ("latency_ms", C.c_double), ("queue_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,6 +70,21 @@ class MdpInfo(C.Structure):
                 ("stored_entries", C.c_int64), ("p_bytes", C.c_int64), ("store", C.c_int),
                 ("fmt", C.c_int), ("gamma", C.c_double), ("persistent_ok", C.c_int32),
                 ("persistent_blocks", C.c_int32)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("slots", C.c_int32), ("prep_threads", C.c_int32),
+                ("block_slices", C.c_int32), ("max_states", C.c_int64), ("hbm_budget", C.c_size_t)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queued", C.c_int32), ("preparing", C.c_int32), ("ready", C.c_int32),
+                ("running", C.c_int32), ("peak_running", C.c_int32), ("xcd_units_cap", C.c_int32),
+                ("arena_bytes", C.c_size_t), ("arena_used", C.c_size_t), ("arena_peak", C.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _P = C.c_void_p
@@ -86,6 +102,13 @@ _sig = {
     "ig_profile_enable": (C.c_int, [_P, C.c_uint]),
     "ig_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
     "ig_last_error": (C.c_char_p, []),
+    "ig_server_config_default": (None, [C.POINTER(ServerConfig)]),
+    "srv_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(_P)]),
+    "srv_submit": (C.c_int, [_P, C.POINTER(MdpDesc), _P, C.POINTER(Params), C.POINTER(C.c_uint64)]),
+    "srv_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int32)]),
+    "srv_result": (C.c_int, [_P, C.c_uint64, _P, _P, C.POINTER(Stats)]),
+    "srv_get_info": (C.c_int, [_P, C.POINTER(ServerInfo)]),
+    "srv_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -209,10 +232,9 @@ class Mdp:
         return {PROFILE_CLASS_NAMES[k]: (ms[k], cnt[k]) for k in range(IG_PROFILE_CLASSES)}
 
 
-def mdp_create(mdp, store: str = "fp64", validate: bool = True, stream=None) -> Mdp:
-    """Create a device MDP from a synth.MDP-like object with host arrays
-    (fmt "csr": row_ptr/col/val; "dense": P).  `mdp.val` / `mdp.P` may be
-    float64, float32 or uint16 (bf16 bit patterns)."""
+def _desc(mdp, store, validate):
+    """MdpDesc for a synth.MDP-like object with host arrays, plus the arrays
+    it points into (to be kept alive by the caller)."""
     d = MdpDesc()
     d.n, d.m, d.gamma = mdp.n, mdp.m, float(mdp.gamma)
     keep = []
@@ -236,6 +258,90 @@ def mdp_create(mdp, store: str = "fp64", validate: bool = True, stream=None) -> 
     d.store = DTYPES[store]
     d.inputs_on_device = 0
     d.validate = int(validate)
+    return d, keep
+
+
+def mdp_create(mdp, store: str = "fp64", validate: bool = True, stream=None) -> Mdp:
+    """Create a device MDP from a synth.MDP-like object with host arrays
+    (fmt "csr": row_ptr/col/val; "dense": P).  `mdp.val` / `mdp.P` may be
+    float64, float32 or uint16 (bf16 bit patterns)."""
+    d, keep = _desc(mdp, store, validate)
     h = C.c_void_p()
     _check(_lib.mdp_create(C.byref(d), stream, C.byref(h)), "mdp_create")
+    del keep
     return Mdp(h, mdp.n, mdp.m, float(mdp.gamma))
+
+
+def server_config_default(**kw) -> ServerConfig:
+    c = ServerConfig()
+    _lib.ig_server_config_default(C.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+class Server:
+    """Continuous-batching solver service (an ig_server_t).  submit() returns
+    a ticket at once; the request's host arrays are held here until result()
+    collects it (the library borrows them)."""
+
+    def __init__(self, config: ServerConfig | None = None, **kw):
+        cfg = config if config is not None else server_config_default(**kw)
+        h = C.c_void_p()
+        _check(_lib.srv_create(C.byref(cfg), C.byref(h)), "srv_create")
+        self.handle = h
+        self.config = cfg
+        self._held = {}
+
+    def submit(self, mdp, params: Params, store: str = "fp32", validate: bool = True, V0=None) -> int:
+        d, keep = _desc(mdp, store, validate)
+        v0 = None
+        if V0 is not None:
+            v0 = np.ascontiguousarray(V0, dtype=np.float64)
+            keep.append(v0)
+        t = C.c_uint64()
+        _check(_lib.srv_submit(self.handle, C.byref(d), _ptr(v0), C.byref(params), C.byref(t)),
+               "srv_submit")
+        self._held[t.value] = (keep, mdp.n)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = C.c_int32()
+        _check(_lib.srv_poll(self.handle, ticket, C.byref(done)), "srv_poll")
+        return bool(done.value)
+
+    def result(self, ticket: int, allow_noconv: bool = False):
+        """Wait for the ticket; returns (V float64[n], pi int32[n], stats dict)."""
+        _, n = self._held[ticket]
+        V = np.zeros(n, np.float64)
+        pi = np.zeros(n, np.int32)
+        st = Stats()
+        rc = _lib.srv_result(self.handle, ticket, V.ctypes.data, pi.ctypes.data, C.byref(st))
+        self._held.pop(ticket, None)
+        _check(rc, "srv_result", (IG_OK, IG_E_NOCONV) if allow_noconv else (IG_OK,))
+        d = st.as_dict()
+        d["status"] = rc
+        return V, pi, d
+
+    def info(self) -> dict:
+        inf = ServerInfo()
+        _check(_lib.srv_get_info(self.handle, C.byref(inf)), "srv_get_info")
+        return inf.as_dict()
+
+    def close(self):
+        if self.handle:
+            _lib.srv_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -4,7 +4,6 @@ header).  No compute call is made."""
 import os
 import re
 import subprocess
-import textwrap
 
 import pytest
 
@@ -38,29 +37,30 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_ctypes_layouts_match_c(tmp_path):
+    """Size of every mirrored struct and the offset of every field."""
     from paper_2211_04299_amd import igmres
     import ctypes
+    pairs = [("ig_mdp_desc", igmres.MdpDesc), ("ig_params", igmres.Params),
+             ("ig_stats", igmres.Stats), ("ig_mdp_info", igmres.MdpInfo),
+             ("ig_server_config", igmres.ServerConfig), ("ig_server_info", igmres.ServerInfo)]
+    body = []
+    for cname, py in pairs:
+        body.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            body.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
     prog = tmp_path / "sz.c"
-    prog.write_text(textwrap.dedent(f"""
-        #include <stdio.h>
-        #include <stddef.h>
-        #include "{HEADER}"
-        int main(void) {{
-          printf("%zu %zu %zu %zu\\n", sizeof(ig_mdp_desc), sizeof(ig_params), sizeof(ig_stats),
-                 sizeof(ig_mdp_info));
-          printf("%zu %zu %zu\\n", offsetof(ig_mdp_desc, validate), offsetof(ig_params, engine),
-                 offsetof(ig_stats, alg_bytes));
-          return 0;
-        }}"""))
+    prog.write_text("#include <stdio.h>\n#include <stddef.h>\n"
+                    f'#include "{HEADER}"\n'
+                    "int main(void) {\n" + "\n".join(body) + "\nreturn 0;\n}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", str(prog), "-o", str(exe)], check=True)
-    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
-    sizes = [int(x) for x in lines[0].split()]
-    assert sizes == [ctypes.sizeof(igmres.MdpDesc), ctypes.sizeof(igmres.Params),
-                     ctypes.sizeof(igmres.Stats), ctypes.sizeof(igmres.MdpInfo)]
-    offs = [int(x) for x in lines[1].split()]
-    assert offs == [igmres.MdpDesc.validate.offset, igmres.Params.engine.offset,
-                    igmres.Stats.alg_bytes.offset]
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = []
+    for _, py in pairs:
+        want.append(ctypes.sizeof(py))
+        want += [getattr(py, f).offset for f, _ in py._fields_]
+    assert got == want
 
 
 def test_params_default_is_theorem1_midpoint():

@@ -78,3 +78,18 @@ def test_storage_wider_than_input():
     m = base()
     m.val = synth.round_values(m.val, "fp32")
     assert "wider" in expect_invalid(m, store="fp64")
+
+
+def test_server_config_rejected_before_device_work():
+    I = igm()
+    for kw in (dict(slots=0), dict(slots=17), dict(prep_threads=0), dict(block_slices=0),
+               dict(max_states=0), dict(hbm_budget=1000)):
+        with pytest.raises(I.IgError) as e:
+            I.Server(**kw)
+        assert e.value.status == I.IG_E_INVALID, kw
+
+
+def test_server_config_default():
+    c = igm().server_config_default()
+    assert (c.slots, c.prep_threads, c.block_slices, c.max_states) == (4, 2, 16, 1 << 19)
+    assert c.hbm_budget == 32 << 30
