@@ -7,10 +7,17 @@ the MDP already resident in HBM.
 
 Prints one JSON line.  Extra keys: "roofline" for the dominant kernel (HIP
 events around its launches during the timed steps; algorithmic bytes per
-launch from the kernel's definition) and "cpu_baseline" (the FP64 oracle's
-literal Algorithm 2 on the host, a bounded sample of solves).
+launch from the kernel's definition), "cpu_baseline" (the FP64 oracle's
+literal Algorithm 2 on the host, a bounded sample of solves) and "serving"
+(continuous batching of a prefix of the serving stream: uneven sparse
+requests, n log-uniform in [1e3, 2e5], m in 2..16, k in 4..32, gamma in
+{0.9, 0.95, 0.99}, FP32-stored P, mixed precision, W = 30, tol 1e-8;
+saturated throughput with every request queued at once, then p50/p99
+latency under Poisson arrivals at 0.8x that throughput, beside the same
+requests solved one at a time by the plain FP64 path).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c4|c3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c4|c3|c5]
+                    [--serve-requests R] [--no-serving]
 """
 import argparse
 import hashlib
@@ -81,12 +88,127 @@ def cpu_baseline(mdp, restart, budget_s=12.0):
                       f"Algorithm 2 (NumPy/SciPy FP64, 1 thread) in {el:.1f} s"}
 
 
+SERVE_W = 30
+SERVE_TOL = 1e-8
+
+
+def serving_requests(synth, count, seed):
+    """The first `count` requests of the seeded serving stream, generated in
+    parallel on the host (values rounded to FP32, as stored)."""
+    from concurrent.futures import ThreadPoolExecutor
+    specs = synth.serving_stream(count, 1.0, seed)
+
+    def make(r):
+        m = r.make(threads=1)
+        m.val = m.val.astype(np.float32)
+        return m
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        mdps = list(ex.map(make, specs))
+    return specs, mdps
+
+
+def serve_once(igmres, mdps, arrivals, prep_threads):
+    """Submit request i at arrivals[i] seconds; returns per-request
+    (latency_s, completion_s, stats) and the server's counters."""
+    srv = igmres.Server(prep_threads=prep_threads)
+    params = [igmres.params_default(m.gamma, restart=SERVE_W, tol=SERVE_TOL, mode="mixed") for m in mdps]
+    t0 = time.perf_counter()
+    tickets, late = [], []
+    for i, mdp in enumerate(mdps):
+        target = t0 + arrivals[i]
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            time.sleep(min(target - now, 0.0005))
+        tickets.append(srv.submit(mdp, params[i], store="fp32", validate=True))
+        late.append(time.perf_counter() - target)
+    out = []
+    for i, t in enumerate(tickets):
+        _, _, st = srv.result(t)
+        lat = late[i] + st["latency_ms"] * 1e-3
+        out.append((lat, arrivals[i] + lat, st))
+    info = srv.info()
+    srv.close()
+    return out, info
+
+
+def sequential_fp64(igmres, torch, mdps, budget_s=15.0):
+    """The plain FP64 path, one request at a time: mdp_create (the stored
+    values in FP64, without the host validation the served requests get),
+    igmres_pi_solve (engine chosen by the library), mdp_destroy."""
+    t0 = time.perf_counter()
+    done = 0
+    for m in mdps:
+        m64 = m.with_values(val=m.val.astype(np.float64))
+        with igmres.mdp_create(m64, store="fp64", validate=False) as h:
+            V = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+            pi = torch.zeros(m.n, dtype=torch.int32, device="cuda")
+            st = h.igmres_pi_solve(V, pi, igmres.params_default(m.gamma, restart=SERVE_W, tol=SERVE_TOL))
+            assert st["converged"] == 1
+        done += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return done, el
+
+
+def serving_leg(igmres, synth, torch, count, seed, load=0.8, prep_threads=4):
+    print(f"[bench] serving: generating {count} requests", file=sys.stderr, flush=True)
+    specs, mdps = serving_requests(synth, count, seed)
+    nnz = np.array([m.nnz for m in mdps], dtype=np.float64)
+    # saturated: every request queued at t = 0
+    print("[bench] serving: saturation run", file=sys.stderr, flush=True)
+    sat, info_sat = serve_once(igmres, mdps, np.zeros(count), prep_threads)
+    makespan = max(c for _, c, _ in sat)
+    lam_sat = count / makespan
+    # Poisson arrivals at `load` x the saturated throughput (same shapes)
+    rate = load * lam_sat
+    arr = np.array([r.arrival for r in synth.serving_stream(count, rate, seed)])
+    print(f"[bench] serving: {lam_sat:.1f} solves/s saturated; Poisson run at {rate:.1f}/s",
+          file=sys.stderr, flush=True)
+    res, info = serve_once(igmres, mdps, arr, prep_threads)
+    lat_ms = np.array([l for l, _, _ in res]) * 1e3
+    span = max(c for _, c, _ in res)
+    sts = [st for _, _, st in res]
+    assert all(st["converged"] == 1 for st in sts), "a served request did not converge"
+    dev_ms = sum(st["time_ms"] for _, _, st in sat)
+    alg = sum(st["alg_bytes"] for _, _, st in sat)
+    print("[bench] serving: sequential FP64 baseline", file=sys.stderr, flush=True)
+    nseq, tseq = sequential_fp64(igmres, torch, mdps)
+    return {
+        "workload": f"first {count} requests of the seeded serving stream (seed {seed}): "
+                    "n log-uniform in [1e3, 2e5], m in 2..16, k in 4..32 uniform successors, "
+                    "Dirichlet(1), gamma in {0.9,0.95,0.99}; FP32-stored P, mixed, W=30, tol 1e-8, "
+                    "host CSR in, V and pi back to the host",
+        "requests": count, "nnz_mean": round(float(nnz.mean())), "nnz_max": int(nnz.max()),
+        "saturated_solves_per_s": round(lam_sat, 2),
+        "offered_load": load, "arrival_rate_per_s": round(rate, 2),
+        "solves_per_s": round(count / span, 2),
+        "p50_latency_ms": round(float(np.percentile(lat_ms, 50)), 3),
+        "p99_latency_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "mean_queue_ms": round(float(np.mean([st["queue_ms"] for st in sts])), 3),
+        "mean_prep_ms": round(float(np.mean([st["prep_ms"] for st in sts])), 3),
+        "mean_device_ms": round(float(np.mean([st["time_ms"] for st in sts])), 3),
+        "max_res_inf": float(max(st["res_inf"] for st in sts)),
+        "saturated_overlap": round(dev_ms / (makespan * 1e3), 3),
+        "saturated_alg_GBps": round(alg / makespan / 1e9, 2),
+        "peak_running": info_sat["peak_running"], "prep_threads": prep_threads,
+        "arena_peak_GiB": round(info_sat["arena_peak"] / 2**30, 3),
+        "sequential_fp64_solves_per_s": round(nseq / tseq, 2), "sequential_fp64_requests": nseq,
+        "speedup_vs_sequential_fp64": round(lam_sat / (nseq / tseq), 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c5"])
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--prep-threads", type=int, default=4)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -111,6 +233,20 @@ def main():
     import torch
 
     from paper_2211_04299_amd import igmres, synth
+
+    if args.workload == "c5":
+        torch.cuda.set_device(0)
+        sv = serving_leg(igmres, synth, torch, args.serve_requests, args.seed,
+                         prep_threads=args.prep_threads)
+        out = {"metric": METRIC, "value": sv["solves_per_s"], "unit": "solves/s",
+               "n_gpus": 1, "steps": sv["requests"], "warmup": 0,
+               "ms_per_step": round(1e3 / sv["solves_per_s"], 4), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+               "config": {"workload": "c5 serving stream: " + sv["workload"]},
+               "p50_latency_ms": sv["p50_latency_ms"], "p99_latency_ms": sv["p99_latency_ms"],
+               "serving": sv, "roofline": None, "cpu_baseline": None}
+        print(json.dumps(out), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     print(f"[bench] generating {args.workload} seed {args.seed}", file=sys.stderr, flush=True)
@@ -178,6 +314,12 @@ def main():
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(mdp, restart)
 
+    h.close()
+    sv = None
+    if not args.no_serving:
+        sv = serving_leg(igmres, synth, torch, args.serve_requests, args.seed,
+                         prep_threads=args.prep_threads)
+
     out = {
         "metric": METRIC, "value": round(1e3 / ms_step, 3), "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
@@ -196,9 +338,9 @@ def main():
                   "alg_GBps_solve": round(st["alg_bytes"] / (ms_step * 1e-3) / 1e9, 2)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": sv,
     }
     print(json.dumps(out), flush=True)
-    h.close()
 
 
 if __name__ == "__main__":

@@ -68,10 +68,10 @@ typedef enum { IG_MODE_FP64 = 0, IG_MODE_MIXED = 1 } ig_mode;
  * bit patterns, uint16).  store is the type P is kept in on the device; it
  * may be narrower than val_type (conversion rounds to nearest even, through
  * fp32 for bf16) but not wider.
- * Validation (when `validate` != 0): 0 <= P <= 1; every row sums to 1 within
- * 1e-10 (FP64 input) or 2^-7 * max(1, row length)^(1/2) (narrow input), and
- * gamma * (largest row sum) < 1; costs finite.  Structural checks (sizes,
- * column range, non-empty rows) are always made. */
+ * Validation (when `validate` != 0): 0 <= P <= 1; no column repeated inside
+ * a row; every row sums to 1 within 1e-10 (FP64 input) or 1/64 (FP32 or BF16
+ * input), and gamma * (largest stored row sum) < 1.  Always checked: sizes,
+ * row_ptr, column range, non-empty rows, finite costs. */
 typedef struct {
   int64_t n;
   int32_t m;
@@ -134,6 +134,7 @@ typedef struct {
   double latency_ms;      /* serving: submission to result ready (host clock);
                              0 for the direct entry points                    */
   double queue_ms;        /* serving: submission to launch                    */
+  double prep_ms;         /* serving: host conversion + upload of the request */
 } ig_stats;
 
 typedef struct ig_mdp_s* ig_mdp_t;

@@ -45,11 +45,23 @@ struct DevRegion {
   size_t size = 0, used = 0;
 };
 
+// Grow-only pinned host buffer that a serving thread reuses for the staging
+// of every request it converts (pinned: the uploads are DMA copies).
+// Buffers outgrown are kept until release() (freeing pinned memory may wait
+// for the device).
+struct PinnedStage {
+  char* buf = nullptr;
+  size_t cap = 0;
+  std::vector<char*> retired;
+  char* get(size_t need);  // nullptr if the allocation fails
+  void release();
+};
+
 struct Mdp {
   int device = 0;
   DevRegion* region = nullptr;          // non-null: allocate from the region
   hipStream_t stream = nullptr;         // stream of the region-mode uploads
-  std::vector<std::shared_ptr<void>> keep;  // host staging alive until uploads finish
+  PinnedStage* stage = nullptr;         // region mode: host staging to use
   bool own_host_mirrors = true;         // hst / hpctl allocated by the handle
   int64_t n = 0;
   int m = 0;

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <memory>
 #include <vector>
 
@@ -114,21 +115,129 @@ ig_status dmalloc(T** p, size_t bytes) {
 }
 
 // host -> device copy; in region mode asynchronous on the handle's stream
-// with the host buffer kept alive by the handle
-template <typename V>
-ig_status upload(Mdp* d, void* dst, V&& vec) {
-  const size_t bytes = vec.size() * sizeof(typename std::decay_t<V>::value_type);
+// (the caller keeps `src` alive until the stream has passed the copy)
+ig_status upload(Mdp* d, void* dst, const void* src, size_t bytes) {
   if (bytes == 0) return IG_OK;
-  if (d->region) {
-    auto holder = std::make_shared<std::decay_t<V>>(std::move(vec));
-    if (hipMemcpyAsync(dst, holder->data(), bytes, hipMemcpyHostToDevice, d->stream) != hipSuccess)
-      return fail(IG_E_DEVICE, "hipMemcpyAsync upload failed");
-    d->keep.push_back(holder);
-    return IG_OK;
+  const hipError_t e = d->region ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, d->stream)
+                                 : hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  return e == hipSuccess ? IG_OK : fail(IG_E_DEVICE, "host to device copy failed");
+}
+
+// Bump allocation inside the host staging buffer of one create.
+struct Staging {
+  char* base = nullptr;
+  size_t used = 0;
+  static size_t round64(size_t b) { return (b + 63) & ~(size_t)63; }
+  template <typename T>
+  T* take(size_t count) {
+    T* p = (T*)(base + used);
+    used += round64(count * sizeof(T));
+    return p;
   }
-  if (hipMemcpy(dst, vec.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
-    return fail(IG_E_DEVICE, "hipMemcpy upload failed");
-  return IG_OK;
+};
+
+// value conversion of the stored transition data
+template <typename T> struct VT_;
+template <> struct VT_<double> {
+  static double in(const double* p, int64_t e) { return p[e]; }
+  static double out(double x, double* o) { *o = x; return x; }
+};
+template <> struct VT_<float> {
+  static double in(const float* p, int64_t e) { return (double)p[e]; }
+  static double out(double x, float* o) { *o = (float)x; return (double)*o; }
+};
+template <> struct VT_<uint16_t> {  // bf16 bit patterns
+  static double in(const uint16_t* p, int64_t e) { return bf16_to_f64(p[e]); }
+  static double out(double x, uint16_t* o) { *o = f32_to_bf16((float)x); return bf16_to_f64(*o); }
+};
+
+struct FillOut {
+  int bad_col = 0, bad_dup = 0, bad_p = 0, bad_sum = 0;
+  double max_stored_sum = 0.0;
+};
+
+// Sliced-ELL image of a CSR MDP: entry (a, j, lane) of slice b at
+// off[b] + ((a*K_b + j) << 6) + lane; padding (j >= row length, lanes past
+// n) is written as column 0, probability 0.  Every entry is written once.
+template <typename IN, typename OUT>
+FillOut fill_sell(int64_t n, int m, const int64_t* rp, const int32_t* col, const IN* val,
+                  const int32_t* width, const int64_t* off, int32_t* scol, OUT* sval, bool validate,
+                  double sum_tol) {
+  const int64_t ns = (n + kSlice - 1) / kSlice;
+  FillOut F;
+  int bad_col = 0, bad_dup = 0, bad_p = 0, bad_sum = 0;
+  double mss = 0.0;
+#pragma omp parallel reduction(+ : bad_col, bad_dup, bad_p, bad_sum) reduction(max : mss)
+  {
+    // duplicate test: stamp[c] == id of the row that last saw column c
+    std::vector<uint32_t> stamp(validate ? (size_t)n : 0, 0u);
+    uint32_t rid = 0;
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t b = 0; b < ns; ++b) {
+      const int Kb = width[b];
+      const int64_t ob = off[b];
+      for (int l = 0; l < kSlice; ++l) {
+        const int64_t s = b * kSlice + l;
+        for (int a = 0; a < m; ++a) {
+          const int64_t base = ob + (((int64_t)a * Kb) << 6) + l;
+          int64_t lo = 0, len = 0;
+          if (s < n) {
+            lo = rp[s * m + a];
+            len = rp[s * m + a + 1] - lo;
+          }
+          if (validate && len > 0 && ++rid == 0) {  // wrapped: forget all stamps
+            std::fill(stamp.begin(), stamp.end(), 0u);
+            rid = 1;
+          }
+          double sum = 0.0, ssum = 0.0;
+          for (int64_t j = 0; j < len; ++j) {
+            const int32_t c = col[lo + j];
+            const bool ok = c >= 0 && c < n;
+            bad_col += !ok;
+            const double p = VT_<IN>::in(val, lo + j);
+            if (validate) {
+              bad_p += !(p >= 0.0 && p <= 1.0);
+              if (ok) {
+                bad_dup += stamp[c] == rid;
+                stamp[c] = rid;
+              }
+            }
+            sum += p;
+            const int64_t pos = base + (j << 6);
+            scol[pos] = ok ? c : 0;
+            ssum += VT_<OUT>::out(p, &sval[pos]);
+          }
+          for (int64_t j = len; j < Kb; ++j) {
+            const int64_t pos = base + (j << 6);
+            scol[pos] = 0;
+            VT_<OUT>::out(0.0, &sval[pos]);
+          }
+          if (s < n) {
+            if (validate && !(std::fabs(sum - 1.0) <= sum_tol)) ++bad_sum;
+            mss = std::max(mss, ssum);
+          }
+        }
+      }
+    }
+  }
+  F.bad_col = bad_col;
+  F.bad_dup = bad_dup;
+  F.bad_p = bad_p;
+  F.bad_sum = bad_sum;
+  F.max_stored_sum = mss;
+  return F;
+}
+
+template <typename IN>
+FillOut fill_sell_in(ig_dtype store, int64_t n, int m, const int64_t* rp, const int32_t* col,
+                     const void* val, const int32_t* width, const int64_t* off, int32_t* scol,
+                     void* sval, bool validate, double sum_tol) {
+  const IN* v = (const IN*)val;
+  switch (store) {
+    case IG_FP64: return fill_sell<IN, double>(n, m, rp, col, v, width, off, scol, (double*)sval, validate, sum_tol);
+    case IG_FP32: return fill_sell<IN, float>(n, m, rp, col, v, width, off, scol, (float*)sval, validate, sum_tol);
+    default: return fill_sell<IN, uint16_t>(n, m, rp, col, v, width, off, scol, (uint16_t*)sval, validate, sum_tol);
+  }
 }
 
 ig_status dzero(Mdp* d, void* dst, size_t bytes) {
@@ -245,22 +354,40 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
   std::vector<double> cost_h = to_host(desc->cost, (size_t)R, ondev, &st);
   if (st) return st;
   const double* cost = ondev ? cost_h.data() : desc->cost;
-  std::vector<double> cost_t((size_t)R);
-  int bad_cost = 0;
-  double cmax = 0.0;
-#pragma omp parallel for reduction(+ : bad_cost) reduction(max : cmax)
-  for (int64_t s = 0; s < n; ++s)
-    for (int a = 0; a < m; ++a) {
-      const double c = cost[s * m + a];
-      if (!std::isfinite(c)) ++bad_cost;
-      else cmax = std::max(cmax, std::fabs(c));
-      cost_t[(size_t)a * n + s] = c;
-    }
-  if (bad_cost) return fail(IG_E_INVALID, "costs must be finite");
-  d->cost_max = cmax;
-
   const double sum_tol = desc->val_type == IG_FP64 ? 1e-10 : 1.0 / 64.0;
   const bool validate = desc->validate != 0;
+
+  // ---- host staging: one buffer for every array that is uploaded ----
+  std::unique_ptr<char[]> local_stage;  // every byte is written before the upload
+  Staging hs;
+  auto stage_get = [&](size_t need) -> ig_status {
+    if (d->stage) {
+      hs.base = d->stage->get(need);
+      if (!hs.base) return fail(IG_E_NOMEM, "pinned staging allocation failed");
+    } else {
+      local_stage.reset(new (std::nothrow) char[need]);
+      if (!local_stage) return fail(IG_E_NOMEM, "host staging allocation failed");
+      hs.base = local_stage.get();
+    }
+    return IG_OK;
+  };
+  double* cost_t = nullptr;
+  auto transpose_costs = [&]() -> ig_status {
+    cost_t = hs.take<double>((size_t)R);
+    int bad_cost = 0;
+    double cmax = 0.0;
+#pragma omp parallel for reduction(+ : bad_cost) reduction(max : cmax)
+    for (int64_t s = 0; s < n; ++s)
+      for (int a = 0; a < m; ++a) {
+        const double c = cost[s * m + a];
+        if (!std::isfinite(c)) ++bad_cost;
+        else cmax = std::max(cmax, std::fabs(c));
+        cost_t[(size_t)a * n + s] = c;
+      }
+    if (bad_cost) return fail(IG_E_INVALID, "costs must be finite");
+    d->cost_max = cmax;
+    return IG_OK;
+  };
 
   if (desc->fmt == IG_FMT_CSR) {
     std::vector<int64_t> rp_h = to_host(desc->row_ptr, (size_t)R + 1, ondev, &st);
@@ -284,7 +411,6 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         return fail(IG_E_DEVICE, "copy of device values failed");
       valp = val_h.data();
     }
-    const ValReader rv{valp, desc->val_type};
 
     // widths per 64-state slice
     const int64_t ns = (n + kSlice - 1) / kSlice;
@@ -299,54 +425,45 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       maxlen = std::max(maxlen, w);
     }
     if (maxlen > n) return fail(IG_E_INVALID, "a row has more entries than states");
-    std::vector<int64_t> off((size_t)ns), offp((size_t)ns);
     int64_t tot = 0, totp = 0;
     for (int64_t b = 0; b < ns; ++b) {
-      off[b] = tot;
-      offp[b] = totp;
       tot += (int64_t)m * width[b] * kSlice;
       totp += (int64_t)width[b] * kSlice;
     }
-    std::vector<int32_t> scol((size_t)tot, 0);
-    std::vector<uint8_t> sval((size_t)tot * d->vb, 0);
-    int bad_col = 0, bad_dup = 0, bad_p = 0, bad_sum = 0;
-    double max_stored_sum = 0.0;
-#pragma omp parallel reduction(+ : bad_col, bad_dup, bad_p, bad_sum) reduction(max : max_stored_sum)
-    {
-      std::vector<int32_t> tmp;
-#pragma omp for schedule(dynamic, 16)
-      for (int64_t b = 0; b < ns; ++b) {
-        const int Kb = width[b];
-        for (int64_t s = b * kSlice; s < std::min(n, (b + 1) * kSlice); ++s) {
-          const int l = (int)(s & (kSlice - 1));
-          for (int a = 0; a < m; ++a) {
-            const int64_t r = s * m + a, lo = rp[r], hi = rp[r + 1];
-            double sum = 0.0, ssum = 0.0;
-            tmp.assign(col + lo, col + hi);
-            for (int64_t e = lo; e < hi; ++e) {
-              const int32_t c = col[e];
-              if (c < 0 || c >= n) ++bad_col;
-              const double p = rv(e);
-              if (validate && !(p >= 0.0 && p <= 1.0)) ++bad_p;
-              sum += p;
-              const int64_t pos = off[b] + (((int64_t)a * Kb + (e - lo)) << 6) + l;
-              scol[pos] = (c >= 0 && c < n) ? c : 0;
-              ssum += store_val(sval.data(), pos, d->store, p);
-            }
-            std::sort(tmp.begin(), tmp.end());
-            for (size_t k = 1; k < tmp.size(); ++k)
-              if (tmp[k] == tmp[k - 1]) ++bad_dup;
-            if (validate && !(std::fabs(sum - 1.0) <= sum_tol)) ++bad_sum;
-            max_stored_sum = std::max(max_stored_sum, ssum);
-          }
-        }
-      }
+    const size_t need = Staging::round64((size_t)R * 8) + Staging::round64((size_t)tot * 4) +
+                        Staging::round64((size_t)tot * d->vb) + 2 * Staging::round64((size_t)ns * 8) +
+                        Staging::round64((size_t)ns * 4);
+    if (ig_status e = stage_get(need)) return e;
+    if (ig_status e = transpose_costs()) return e;
+    int64_t* off = hs.take<int64_t>((size_t)ns);
+    int64_t* offp = hs.take<int64_t>((size_t)ns);
+    int32_t* wid = hs.take<int32_t>((size_t)ns);
+    int32_t* scol = hs.take<int32_t>((size_t)tot);
+    void* sval = hs.take<char>((size_t)tot * d->vb);
+    for (int64_t b = 0, t = 0, tp = 0; b < ns; ++b) {
+      off[b] = t;
+      offp[b] = tp;
+      wid[b] = width[b];
+      t += (int64_t)m * width[b] * kSlice;
+      tp += (int64_t)width[b] * kSlice;
     }
-    if (bad_col) return fail(IG_E_INVALID, "column index out of range");
-    if (bad_dup) return fail(IG_E_INVALID, "repeated column inside a row");
-    if (bad_p) return fail(IG_E_INVALID, "probabilities must lie in [0,1]");
-    if (bad_sum) return fail(IG_E_INVALID, "a transition row does not sum to 1");
-    if (validate && !(d->gamma * max_stored_sum < 1.0))
+    FillOut F;
+    switch (desc->val_type) {
+      case IG_FP64:
+        F = fill_sell_in<double>(d->store, n, m, rp, col, valp, wid, off, scol, sval, validate, sum_tol);
+        break;
+      case IG_FP32:
+        F = fill_sell_in<float>(d->store, n, m, rp, col, valp, wid, off, scol, sval, validate, sum_tol);
+        break;
+      default:
+        F = fill_sell_in<uint16_t>(d->store, n, m, rp, col, valp, wid, off, scol, sval, validate, sum_tol);
+        break;
+    }
+    if (F.bad_col) return fail(IG_E_INVALID, "column index out of range");
+    if (F.bad_dup) return fail(IG_E_INVALID, "repeated column inside a row");
+    if (F.bad_p) return fail(IG_E_INVALID, "probabilities must lie in [0,1]");
+    if (F.bad_sum) return fail(IG_E_INVALID, "a transition row does not sum to 1");
+    if (validate && !(d->gamma * F.max_stored_sum < 1.0))
       return fail(IG_E_INVALID, "gamma * (largest stored row sum) must be < 1");
 
     d->nslices = ns;
@@ -360,11 +477,11 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         dmalloc(&d->width, (size_t)ns * 4) || dmalloc(&d->pcol, (size_t)totp * 4) ||
         dmalloc(&d->pval, (size_t)totp * d->vb))
       return IG_E_NOMEM;
-    if (ig_status e = upload(d, d->col, std::move(scol))) return e;
-    if (ig_status e = upload(d, d->val, std::move(sval))) return e;
-    if (ig_status e = upload(d, d->off, std::move(off))) return e;
-    if (ig_status e = upload(d, d->offp, std::move(offp))) return e;
-    if (ig_status e = upload(d, d->width, std::vector<int32_t>(width))) return e;
+    if (ig_status e = upload(d, d->col, scol, (size_t)tot * 4)) return e;
+    if (ig_status e = upload(d, d->val, sval, (size_t)tot * d->vb)) return e;
+    if (ig_status e = upload(d, d->off, off, (size_t)ns * 8)) return e;
+    if (ig_status e = upload(d, d->offp, offp, (size_t)ns * 8)) return e;
+    if (ig_status e = upload(d, d->width, wid, (size_t)ns * 4)) return e;
     if (ig_status e = dzero(d, d->pcol, (size_t)totp * 4)) return e;
     if (ig_status e = dzero(d, d->pval, (size_t)totp * d->vb)) return e;
 
@@ -384,7 +501,10 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       valp = val_h.data();
     }
     const ValReader rv{valp, desc->val_type};
-    std::vector<uint8_t> sval((size_t)total * d->vb);
+    if (ig_status e = stage_get(Staging::round64((size_t)R * 8) + Staging::round64((size_t)total * d->vb)))
+      return e;
+    if (ig_status e = transpose_costs()) return e;
+    uint8_t* sval = hs.take<uint8_t>((size_t)total * d->vb);
     int bad_p = 0, bad_sum = 0;
     double max_stored_sum = 0.0;
 #pragma omp parallel for reduction(+ : bad_p, bad_sum) reduction(max : max_stored_sum) schedule(dynamic, 64)
@@ -394,7 +514,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         const double p = rv(e);
         if (validate && !(p >= 0.0 && p <= 1.0)) ++bad_p;
         sum += p;
-        ssum += store_val(sval.data(), e, d->store, p);
+        ssum += store_val(sval, e, d->store, p);
       }
       if (validate && !(std::fabs(sum - 1.0) <= sum_tol)) ++bad_sum;
       max_stored_sum = std::max(max_stored_sum, ssum);
@@ -407,7 +527,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     d->stored = total;
     d->maxK = (int)n;
     if (dmalloc(&d->P, (size_t)total * d->vb)) return IG_E_NOMEM;
-    if (ig_status e = upload(d, d->P, std::move(sval))) return e;
+    if (ig_status e = upload(d, d->P, sval, (size_t)total * d->vb)) return e;
   }
 
   if (dmalloc(&d->cost, (size_t)R * 8) || dmalloc(&d->cpi, (size_t)n * 8) ||
@@ -415,7 +535,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       dmalloc(&d->part, part_doubles(d->n) * 8) ||
       dmalloc(&d->pctl, sizeof(PCtl)))
     return IG_E_NOMEM;
-  if (ig_status e = upload(d, d->cost, std::move(cost_t))) return e;
+  if (ig_status e = upload(d, d->cost, cost_t, (size_t)R * 8)) return e;
   if (ig_status e = dzero(d, d->st, sizeof(DevStatus))) return e;
   if (ig_status e = dzero(d, d->gs, sizeof(GivensState))) return e;
   if (d->own_host_mirrors &&
@@ -431,9 +551,34 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
   IG_HIP(hipDeviceGetAttribute(&d->num_cu, hipDeviceAttributeMultiprocessorCount, d->device));
   IG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, d->device));
   d->coop = coop != 0;
+  // uploads from the local staging must finish before it goes away
   if (!d->region) IG_HIP(hipDeviceSynchronize());
+  else if (!d->stage) IG_HIP(hipStreamSynchronize(d->stream));
   (void)stream;
   return IG_OK;
+}
+
+char* PinnedStage::get(size_t need) {
+  if (need <= cap) return buf;
+  if (buf) retired.push_back(buf);
+  buf = nullptr;
+  const size_t want = std::max(need, 2 * cap);
+  if (hipHostMalloc((void**)&buf, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    buf = nullptr;
+    cap = 0;
+    return nullptr;
+  }
+  cap = want;
+  return buf;
+}
+
+void PinnedStage::release() {
+  for (char* p : retired) (void)hipHostFree(p);
+  retired.clear();
+  if (buf) (void)hipHostFree(buf);
+  buf = nullptr;
+  cap = 0;
 }
 
 // create_impl with the handle's region (if any) as the allocation target

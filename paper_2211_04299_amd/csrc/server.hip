@@ -157,11 +157,12 @@ void set_error(Req* r, ig_status e) {
 }
 
 // Conversion and upload of one request (prep thread, outside the lock).
-ig_status prepare(Server& S, Req* r, hipStream_t ps) {
+ig_status prepare(Server& S, Req* r, hipStream_t ps, PinnedStage* stage) {
   auto d = std::make_unique<Mdp>();
   d->device = S.cfg.device;
   d->region = &r->region;
   d->stream = ps;
+  d->stage = stage;
   d->own_host_mirrors = false;
   if (ig_status e = create_in(&r->desc, d.get())) {
     release_handle(d.get());
@@ -182,9 +183,10 @@ ig_status prepare(Server& S, Req* r, hipStream_t ps) {
   if (!e && hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming) != hipSuccess)
     e = fail(IG_E_DEVICE, "hipEventCreate failed");
   if (!e && hipEventRecord(r->uploaded, ps) != hipSuccess) e = fail(IG_E_DEVICE, "hipEventRecord failed");
-  // the host staging of the uploads (and the borrowed V0) must outlive them
+  // the staging buffer (and the borrowed V0) is reused / returned only
+  // after the uploads are done
   if (hipStreamSynchronize(ps) != hipSuccess && !e) e = fail(IG_E_DEVICE, "upload failed");
-  d->keep.clear();
+  d->stage = nullptr;
   if (!e && !persistent_fits(*d)) e = fail(IG_E_TOO_LARGE, "shape does not fit the persistent engine");
   if (e) {
     release_handle(d.get());
@@ -205,6 +207,7 @@ void prep_loop(Server* Sp, int omp_threads) {
   omp_set_num_threads(std::max(1, omp_threads));
   hipStream_t ps = nullptr;
   (void)hipStreamCreateWithFlags(&ps, hipStreamNonBlocking);
+  PinnedStage stage;  // this thread's staging, reused for every request
   std::unique_lock<std::mutex> lk(S.mu);
   for (;;) {
     S.cv_prep.wait(lk, [&] { return S.stop || !S.queued.empty(); });
@@ -245,7 +248,9 @@ void prep_loop(Server* Sp, int omp_threads) {
       r->region.base = S.base + r->off;
       r->region.size = bytes;
       r->region.used = 0;
-      if (ig_status e2 = prepare(S, r, ps)) set_error(r, e2);
+      const Clock::time_point tp = Clock::now();
+      if (ig_status e2 = prepare(S, r, ps, &stage)) set_error(r, e2);
+      r->st.prep_ms = ms_between(tp, Clock::now());
     }
 
     lk.lock();
@@ -269,7 +274,11 @@ void prep_loop(Server* Sp, int omp_threads) {
     }
   }
   lk.unlock();
-  if (ps) (void)hipStreamDestroy(ps);
+  if (ps) {
+    (void)hipStreamSynchronize(ps);
+    (void)hipStreamDestroy(ps);
+  }
+  stage.release();
 }
 
 // Enqueue request r on slot k (scheduler thread, outside the lock).
@@ -449,7 +458,7 @@ ig_status srv_create(const ig_server_config* cfg, ig_server_t* out) {
       return fail(IG_E_NOMEM, "hipHostMalloc of result buffers failed");
     }
   }
-  const int hw = std::max(1, omp_get_num_procs());
+  const int hw = std::max(1, omp_get_max_threads());
   const int per = std::max(1, hw / cfg->prep_threads);
   try {
     for (int t = 0; t < cfg->prep_threads; ++t) S.preps.emplace_back(prep_loop, &S, per);

@@ -59,7 +59,8 @@ class Stats(C.Structure):
                 ("bellman_passes", C.c_int32), ("explicit_residuals", C.c_int32),
                 ("breakdowns", C.c_int32), ("stagnations", C.c_int32), ("converged", C.c_int32),
                 ("res_inf", C.c_double), ("cert_bound", C.c_double), ("time_ms", C.c_double),
-                ("alg_bytes", C.c_double), ("latency_ms", C.c_double), ("queue_ms", C.c_double)]
+                ("alg_bytes", C.c_double), ("latency_ms", C.c_double), ("queue_ms", C.c_double),
+                ("prep_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
