@@ -188,6 +188,10 @@ void launch_form_qi(Mdp& d, bool fp32, int c, const void* w1, hipStream_t s);
 void launch_dots(Mdp& d, bool fp32, int cnt, const void* v, bool givens, bool with_impl,
                  hipStream_t s);
 // w1 = y - sum_{j<cnt} gs->h_j Q_j
+// one Arnoldi step's orthogonalisation (after the J-apply): fused two-pass
+// form for columns up to gs_fused_max, else the four-kernel sequence
+void launch_gs_step(Mdp& d, bool fp32, int c, const void* y, void* w1, hipStream_t s);
+int gs_fused_max(bool fp32);
 void launch_axpy(Mdp& d, bool fp32, int cnt, const void* y, void* w1, hipStream_t s);
 // V = Vb + sum_{j<i} y_j Q_j with R y = g_hat (back substitution per block)
 void launch_update(Mdp& d, bool fp32, int i, const double* Vb, double* V, hipStream_t s);

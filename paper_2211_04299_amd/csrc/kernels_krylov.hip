@@ -152,6 +152,163 @@ __global__ __launch_bounds__(kBlock) void k_form_qi(XT* __restrict__ Q, int64_t 
   if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartStride + kPartStride - 1] = v[0];
 }
 
+// ---- fused Gram-Schmidt step: two passes over the basis per column -------
+// Every thread owns one state row at a time and keeps that row of the basis
+// (at most JM columns) in registers, so each pass reads the basis once.
+//   pass A (column c): Q_c = (w1 - sum_{j<c} d_j Q_j) / eta, the implicit
+//     residual sum_{j<=c} z_j Q_j of column c-1, and h_j = <Q_j, y>, j <= c
+//     (at c = 0 only h_0 = <Q_0, y>)
+//   pass B: w1 = y - sum_{j<=c} h_j Q_j, d_j = <Q_j, w1>, sigma = ||w1||^2
+// Partials: per block, columns 0..cnt-1 (+ sigma at cnt for B; the implicit
+// residual's max in the spare last column for A).
+
+template <int JM>
+__device__ __forceinline__ void store_cols(double (&acc)[JM], int cnt, double* mypart) {
+  constexpr int op8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j0 = 0; j0 < JM; j0 += 8) {
+    if (j0 >= cnt) break;  // uniform over the block
+    double t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = acc[j0 + k];
+    block_reduce<8>(t, op8);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (j0 + k < cnt) mypart[j0 + k] = t[k];
+    }
+  }
+}
+
+// Row of the basis at state s into q[0..JM): column min(j, cnt-1) (column 0
+// when cnt == 0), so every load is in bounds and finite and all JM loads are
+// issued back to back without branches (the repeats hit in cache).  Callers
+// give columns >= cnt zero coefficients and discard their dot products.
+template <typename XT, int JM>
+__device__ __forceinline__ void load_row(const XT* __restrict__ Q, int64_t n, int cnt, int64_t s,
+                                         XT (&q)[JM]) {
+  const int last = cnt > 0 ? cnt - 1 : 0;
+#pragma unroll
+  for (int j = 0; j < JM; ++j) q[j] = Q[(int64_t)min(j, last) * n + s];
+}
+
+template <typename XT, int JM>
+__global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, int c,
+                                                 const XT* __restrict__ w1,
+                                                 const XT* __restrict__ y,
+                                                 const GivensState* __restrict__ gs,
+                                                 const DevStatus* __restrict__ st,
+                                                 double* __restrict__ part) {
+  __shared__ double dd[JM], zz[JM];
+  for (int j = threadIdx.x; j < JM; j += kBlock) {
+    dd[j] = j < c ? gs->h2[j] : 0.0;
+    zz[j] = j < c ? gs->z[j] : 0.0;
+  }
+  __syncthreads();
+  const double zc = gs->z[c];
+  const double inv = c > 0 ? 1.0 / st->eta : 0.0;
+  double acc[JM];
+#pragma unroll
+  for (int j = 0; j < JM; ++j) acc[j] = 0.0;
+  double accc = 0.0, rmax = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  XT* qc = Q + (int64_t)c * n;
+  const int64_t s0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // y and w1 of the next row are loaded one iteration ahead (index clamped
+  // into range), so that their latency overlaps the basis loads
+  XT yn = y[min(s0, n - 1)], wn = w1[min(s0, n - 1)];
+  for (int64_t s = s0; s < n; s += stride) {
+    // re-read the LDS coefficients per row instead of holding 2*JM doubles
+    // in registers
+    asm volatile("" ::: "memory");
+    const XT yv = yn, wv = wn, q0v = Q[s];
+    yn = y[min(s + stride, n - 1)];
+    wn = w1[min(s + stride, n - 1)];
+    XT q[JM];
+    load_row<XT, JM>(Q, n, c, s, q);
+    const double ys = to_d(yv);
+    double corr0 = 0.0, corr1 = 0.0, r0 = 0.0, r1 = 0.0;
+#pragma unroll
+    for (int g = 0; g < JM; g += 8) {
+      asm volatile("" ::: "memory");  // at most 8 coefficient pairs live
+#pragma unroll
+      for (int j = g; j < g + 8; j += 2) {
+        corr0 = fma(dd[j], to_d(q[j]), corr0);
+        r0 = fma(zz[j], to_d(q[j]), r0);
+        corr1 = fma(dd[j + 1], to_d(q[j + 1]), corr1);
+        r1 = fma(zz[j + 1], to_d(q[j + 1]), r1);
+      }
+    }
+    const XT qx = from_d<XT>((to_d(wv) - (corr0 + corr1)) * inv);
+    if (c > 0) qc[s] = qx;
+    const double qcs = c > 0 ? to_d(qx) : to_d(q0v);
+    const double rr = fabs(fma(zc, qcs, r0 + r1));
+    rmax = c > 0 ? fmax(rmax, rr) : rmax;
+#pragma unroll
+    for (int j = 0; j < JM; ++j) acc[j] = fma(to_d(q[j]), ys, acc[j]);
+    accc = fma(qcs, ys, accc);
+  }
+#pragma unroll
+  for (int j = 0; j < JM; ++j)
+    if (j == c) acc[j] = accc;
+  double* mypart = part + (int64_t)blockIdx.x * kPartStride;
+  store_cols<JM>(acc, c + 1, mypart);
+  if (c > 0) {
+    double v[1] = {rmax};
+    const int op[1] = {1};
+    block_reduce<1>(v, op);
+    if (threadIdx.x == 0) mypart[kPartStride - 1] = v[0];
+  }
+}
+
+template <typename XT, int JM>
+__global__ __launch_bounds__(kBlock) void k_gs_b(const XT* __restrict__ Q, int64_t n, int cnt,
+                                                 const GivensState* __restrict__ gs,
+                                                 const XT* __restrict__ y, XT* __restrict__ w1,
+                                                 double* __restrict__ part) {
+  __shared__ double h[JM];
+  for (int j = threadIdx.x; j < JM; j += kBlock) h[j] = j < cnt ? gs->h[j] : 0.0;
+  __syncthreads();
+  double acc[JM];
+#pragma unroll
+  for (int j = 0; j < JM; ++j) acc[j] = 0.0;
+  double nrm = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t s0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  XT yn = y[min(s0, n - 1)];  // one row ahead, index clamped into range
+  for (int64_t s = s0; s < n; s += stride) {
+    asm volatile("" ::: "memory");
+    const XT yv = yn;
+    yn = y[min(s + stride, n - 1)];
+    XT q[JM];
+    load_row<XT, JM>(Q, n, cnt, s, q);
+    double a0 = to_d(yv), a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+    for (int g = 0; g < JM; g += 8) {
+      asm volatile("" ::: "memory");  // at most 8 coefficients live
+#pragma unroll
+      for (int j = g; j < g + 8; j += 4) {
+        a0 = fma(-h[j], to_d(q[j]), a0);
+        a1 = fma(-h[j + 1], to_d(q[j + 1]), a1);
+        a2 = fma(-h[j + 2], to_d(q[j + 2]), a2);
+        a3 = fma(-h[j + 3], to_d(q[j + 3]), a3);
+      }
+    }
+    const XT wx = from_d<XT>((a0 + a1) + (a2 + a3));
+    w1[s] = wx;
+    const double wd = to_d(wx);
+#pragma unroll
+    for (int j = 0; j < JM; ++j) acc[j] = fma(to_d(q[j]), wd, acc[j]);
+    nrm = fma(wd, wd, nrm);
+  }
+  double* mypart = part + (int64_t)blockIdx.x * kPartStride;
+  store_cols<JM>(acc, cnt, mypart);
+  double v[1] = {nrm};
+  const int op[1] = {0};
+  block_reduce<1>(v, op);
+  if (threadIdx.x == 0) mypart[cnt] = v[0];
+}
+
 // Q_0 = r / beta, beta = sqrt(*l2sq); Givens state reset (block 0).
 template <typename XT>
 __global__ __launch_bounds__(kBlock) void k_form_q0(const double* __restrict__ r,
@@ -245,6 +402,75 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
     }
     __syncthreads();
   }
+  if (kind == FIN_GIVENS) {
+    // red = [d_0..d_col, sigma]; gs->h = first-pass coefficients of column
+    // col.  The state is staged in LDS so that the serial rotation sweep
+    // touches no global memory.
+    __shared__ double h[kMaxW + 2], cs[kMaxW + 1], sn[kMaxW + 1], z[kMaxW + 2], g2[2];
+    __shared__ double eta_s;
+    const int col = cnt - 2;
+    for (int j = threadIdx.x; j < col; j += kFinT) {
+      cs[j] = gs->cs[j];
+      sn[j] = gs->sn[j];
+    }
+    for (int j = threadIdx.x; j <= col; j += kFinT) h[j] = gs->h[j] + red[j];
+    if (threadIdx.x == 0) {
+      g2[0] = gs->g[col];
+      double dd = 0.0;
+      for (int j = 0; j <= col; ++j) dd = fma(red[j], red[j], dd);
+      eta_s = sqrt(fmax(red[col + 1] - dd, 0.0));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      h[col + 1] = eta_s;
+      for (int j = 0; j < col; ++j) {  // previous rotations
+        const double t = cs[j] * h[j] + sn[j] * h[j + 1];
+        h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
+        h[j] = t;
+      }
+      const double r = hypot(h[col], h[col + 1]);
+      double c = 1.0, s = 0.0;
+      if (r > 0.0) {
+        c = h[col] / r;
+        s = h[col + 1] / r;
+      }
+      cs[col] = c;
+      sn[col] = s;
+      h[col] = r;
+      h[col + 1] = 0.0;
+      const double gc = g2[0];
+      g2[1] = -s * gc;
+      g2[0] = c * gc;
+      // residual of this column's iterate in basis coordinates
+      double v = g2[1];
+      for (int j = col; j >= 0; --j) {
+        z[j + 1] = cs[j] * v;
+        v = -sn[j] * v;
+      }
+      z[0] = v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j <= col; j += kFinT) {
+      gs->h2[j] = red[j];
+      gs->h[j] = h[j];
+      gs->R[(int64_t)col * (kMaxW + 1) + j] = h[j];
+    }
+    for (int j = threadIdx.x; j <= col + 1; j += kFinT) gs->z[j] = z[j];
+    if (threadIdx.x == 0) {
+      gs->h[col + 1] = 0.0;
+      gs->cs[col] = cs[col];
+      gs->sn[col] = sn[col];
+      gs->g[col] = g2[0];
+      gs->g[col + 1] = g2[1];
+      st->eta = eta_s;
+      st->rho = fabs(g2[1]);
+    }
+    return;
+  }
+  if (kind == FIN_DOTS) {
+    for (int j = threadIdx.x; j < cnt; j += kFinT) gs->h[j] = red[j];
+    return;
+  }
   if (threadIdx.x != 0) return;
   switch (kind) {
     case FIN_BELLMAN:
@@ -268,50 +494,6 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
     case FIN_IMPL:
       st->res_impl = red[0];
       break;
-    case FIN_DOTS:
-      for (int j = 0; j < cnt; ++j) gs->h[j] = red[j];
-      break;
-    case FIN_GIVENS: {
-      // red = [d_0..d_col, sigma]; gs->h = first-pass coefficients of column col
-      const int col = cnt - 2;
-      double dd = 0.0;
-      for (int j = 0; j <= col; ++j) {
-        gs->h2[j] = red[j];
-        dd = fma(red[j], red[j], dd);
-      }
-      const double eta = sqrt(fmax(red[col + 1] - dd, 0.0));
-      double* h = gs->h;
-      for (int j = 0; j <= col; ++j) h[j] += red[j];
-      h[col + 1] = eta;
-      for (int j = 0; j < col; ++j) {  // previous rotations
-        const double t = gs->cs[j] * h[j] + gs->sn[j] * h[j + 1];
-        h[j + 1] = -gs->sn[j] * h[j] + gs->cs[j] * h[j + 1];
-        h[j] = t;
-      }
-      const double r = hypot(h[col], h[col + 1]);
-      double cs = 1.0, sn = 0.0;
-      if (r > 0.0) {
-        cs = h[col] / r;
-        sn = h[col + 1] / r;
-      }
-      gs->cs[col] = cs;
-      gs->sn[col] = sn;
-      h[col] = r;
-      h[col + 1] = 0.0;
-      gs->g[col + 1] = -sn * gs->g[col];
-      gs->g[col] = cs * gs->g[col];
-      for (int j = 0; j <= col; ++j) gs->R[(int64_t)col * (kMaxW + 1) + j] = h[j];
-      // residual of this column's iterate in basis coordinates
-      double v = gs->g[col + 1];
-      for (int j = col; j >= 0; --j) {
-        gs->z[j + 1] = gs->cs[j] * v;
-        v = -gs->sn[j] * v;
-      }
-      gs->z[0] = v;
-      st->eta = eta;
-      st->rho = fabs(gs->g[col + 1]);
-      break;
-    }
     default:
       break;
   }
@@ -376,6 +558,54 @@ void launch_dots(Mdp& d, bool fp32, int cnt, const void* v, bool givens, bool wi
   }
   launch_finalize(d, givens ? FIN_GIVENS : FIN_DOTS, gs_grid(d), s, givens ? cnt + 1 : cnt,
                   with_impl);
+}
+
+namespace {
+
+template <typename XT, int JM>
+void gs_step_typed(Mdp& d, int c, const void* y, void* w1, hipStream_t s) {
+  const int nb = gs_grid(d);
+  {
+    ProfScope p(d, KC_GS, s);
+    hipLaunchKernelGGL((k_gs_a<XT, JM>), dim3(nb), dim3(kBlock), 0, s, (XT*)d.ws.Q, d.n, c,
+                       (const XT*)w1, (const XT*)y, (const GivensState*)d.gs,
+                       (const DevStatus*)d.st, d.part);
+  }
+  launch_finalize(d, FIN_DOTS, nb, s, c + 1, c > 0);
+  {
+    ProfScope p(d, KC_GS, s);
+    hipLaunchKernelGGL((k_gs_b<XT, JM>), dim3(nb), dim3(kBlock), 0, s, (const XT*)d.ws.Q, d.n,
+                       c + 1, (const GivensState*)d.gs, (const XT*)y, (XT*)w1, d.part);
+  }
+  launch_finalize(d, FIN_GIVENS, nb, s, c + 2, false);
+}
+
+template <typename XT>
+bool gs_step_bucket(Mdp& d, int c, const void* y, void* w1, hipStream_t s) {
+  const int need = c + 1;
+  if (need <= 8) gs_step_typed<XT, 8>(d, c, y, w1, s);
+  else if (need <= 16) gs_step_typed<XT, 16>(d, c, y, w1, s);
+  else if (need <= 32) gs_step_typed<XT, 32>(d, c, y, w1, s);
+  else if (sizeof(XT) == 4 && need <= 48) gs_step_typed<XT, 48>(d, c, y, w1, s);
+  else if (sizeof(XT) == 4 && need <= 64) gs_step_typed<XT, 64>(d, c, y, w1, s);
+  else return false;
+  return true;
+}
+
+}  // namespace
+
+int gs_fused_max(bool fp32) { return fp32 ? 64 : 32; }
+
+void launch_gs_step(Mdp& d, bool fp32, int c, const void* y, void* w1, hipStream_t s) {
+  const bool done = fp32 ? gs_step_bucket<float>(d, c, y, w1, s)
+                         : gs_step_bucket<double>(d, c, y, w1, s);
+  if (done) return;
+  // columns beyond the register buckets: separate formation, projection,
+  // update and second projection
+  if (c > 0) launch_form_qi(d, fp32, c, w1, s);
+  launch_dots(d, fp32, c + 1, y, false, c > 0, s);
+  launch_axpy(d, fp32, c + 1, y, w1, s);
+  launch_dots(d, fp32, c + 1, w1, true, false, s);
 }
 
 void launch_axpy(Mdp& d, bool fp32, int cnt, const void* y, void* w1, hipStream_t s) {

@@ -20,6 +20,56 @@ namespace {
 
 constexpr int kU = 8;  // entries per unrolled chunk
 
+// Software-pipelined pass over F entries of one lane, entry f at
+// base + f * step: the column and value loads of chunk k+1 are issued before
+// the gathers of chunk k, so a chunk costs one memory round trip instead of
+// two.  consume(v, xs) is called per entry, in order, with the value and
+// the gathered x[col] * scale, both converted to AT.
+template <typename VT, typename XT, typename AT, typename Consume>
+__device__ __forceinline__ void ell_stream(const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, int64_t base,
+                                           int64_t step, int F, const XT* __restrict__ x,
+                                           XT scale, Consume&& consume) {
+  if (F <= 0) return;
+  int32_t c[kU], cn[kU];
+  VT v[kU], vn[kU];
+  auto load = [&](int f0, int32_t(&cc)[kU], VT(&vv)[kU]) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t e = base + (int64_t)min(f0 + u, F - 1) * step;  // clamped: in range
+      cc[u] = col[e];
+      vv[u] = val[e];
+    }
+  };
+  auto use = [&](int f0, const int32_t(&cc)[kU], const VT(&vv)[kU]) {
+    XT xv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) xv[u] = x[cc[u]];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (f0 + u < F) {
+        if constexpr (sizeof(AT) == 8)
+          consume(to_d(vv[u]), (AT)(xv[u] * scale));
+        else
+          consume(to_f(vv[u]), (AT)(xv[u] * scale));
+      }
+    }
+  };
+  load(0, c, v);
+  int f0 = 0;
+  for (; f0 + kU < F; f0 += 2 * kU) {
+    load(f0 + kU, cn, vn);
+    use(f0, c, v);
+    if (f0 + 2 * kU >= F) {
+      use(f0 + kU, cn, vn);
+      return;
+    }
+    load(f0 + 2 * kU, c, v);
+    use(f0 + kU, cn, vn);
+  }
+  use(f0, c, v);
+}
+
 // sum_j val[e_j] * x[col[e_j]] * scale over the entries j = g, g+G, ... < K of
 // one sliced-ELL row starting at `base` (entry j at base + (j << 6)).
 template <typename VT, typename XT, typename AT, int G>
@@ -27,30 +77,14 @@ __device__ __forceinline__ AT ell_row(const int32_t* __restrict__ col, const VT*
                                       int64_t base, int K, int g, const XT* __restrict__ x,
                                       XT scale) {
   AT acc = 0;
-  for (int j0 = g; j0 < K; j0 += kU * G) {
-    int32_t c[kU];
-    VT v[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int j = j0 + u * G;
-      if (j < K) {
-        const int64_t e = base + ((int64_t)j << 6);
-        c[u] = col[e];
-        v[u] = val[e];
-      } else {
-        c[u] = 0;
-        v[u] = VT{};
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const XT xv = x[c[u]] * scale;
-      if constexpr (sizeof(AT) == 8)
-        acc = fma(to_d(v[u]), (AT)xv, acc);
-      else
-        acc = fmaf(to_f(v[u]), (AT)xv, acc);
-    }
-  }
+  const int F = K > g ? (K - g + G - 1) / G : 0;
+  ell_stream<VT, XT, AT>(col, val, base + ((int64_t)g << 6), (int64_t)G << 6, F, x, scale,
+                         [&](AT pv, AT xv) {
+                           if constexpr (sizeof(AT) == 8)
+                             acc = fma(pv, xv, acc);
+                           else
+                             acc = fmaf(pv, xv, acc);
+                         });
   return acc;
 }
 
@@ -88,16 +122,36 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
 
     double best = INFINITY, qinc = INFINITY;
     int besta = m;  // sentinel: no finite candidate yet
-    for (int a = g; a < m; a += G) {
-      const double acc = ell_row<VT, double, double, 1>(P.col, P.val, ob + (((int64_t)a * Kb) << 6),
-                                                        Kb, 0, V, 1.0);
-      const double q = cost[(int64_t)a * n + sc] + gamma * acc;
+    auto candidate = [&](int a, double q) {
       if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;  // NaN or +-Inf
       if (q < best) {  // actions visited in increasing order: lowest index wins ties
         best = q;
         besta = a;
       }
       if (a == inc) qinc = q;
+    };
+    if constexpr (G == 1) {
+      // one lane per state: rows a = 0..m-1 of the slice are consecutive, so
+      // the m*Kb entries form one pipelined stream; the cost of row a is
+      // loaded when the row starts and used when it ends
+      double acc = 0.0, cst = cost[sc];
+      int j = 0, a = 0;
+      ell_stream<VT, double, double>(P.col, P.val, ob, kSlice, m * Kb, V, 1.0,
+                                     [&](double pv, double xv) {
+                                       acc = fma(pv, xv, acc);
+                                       if (++j == Kb) {
+                                         candidate(a, cst + gamma * acc);
+                                         acc = 0.0;
+                                         j = 0;
+                                         if (++a < m) cst = cost[(int64_t)a * n + sc];
+                                       }
+                                     });
+    } else {
+      for (int a = g; a < m; a += G) {
+        const double acc = ell_row<VT, double, double, 1>(
+            P.col, P.val, ob + (((int64_t)a * Kb) << 6), Kb, 0, V, 1.0);
+        candidate(a, cost[(int64_t)a * n + sc] + gamma * acc);
+      }
     }
 #pragma unroll
     for (int o = S; o < kWave; o <<= 1) {

@@ -57,10 +57,14 @@ struct Bytes {
   double nnz_pi() const { return (double)d.nnz / d.m; }
   double bellman() const { return d.nnz * entry() + d.n * (double)d.m * 8 + d.n * (8.0 + 8 + 4); }
   double japply(bool fp32) const { return nnz_pi() * entry() + d.n * (fp32 ? 4.0 : 8.0) * 2; }
-  // form Q_c (reads c basis columns and w1, writes Q_c), two dot passes over
-  // c+1 columns, the axpy over c+1 columns (reads y, writes w1)
+  // Orthogonalisation of column c.  Fused form: pass A reads Q_0..Q_{c-1},
+  // w1 and y and writes Q_c (c = 0: reads Q_0 and y); pass B reads
+  // Q_0..Q_c and y and writes w1.  Separate form: formation (c columns + w1
+  // in, Q_c out), two projections over c+1 columns and the update.
   double gs(bool fp32, int c) const {
     const double xb = fp32 ? 4 : 8;
+    if (c + 1 <= gs_fused_max(fp32))
+      return d.n * xb * ((c > 0 ? c + 3.0 : 2.0) + (c + 3.0));
     return d.n * xb * ((c + 2.0) + (c + 2.0) + (c + 3.0) + (c + 2.0));
   }
   double update(bool fp32, int i) const { return d.n * (i * (fp32 ? 4.0 : 8.0) + 16); }
@@ -114,15 +118,11 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
   };
 
   for (int c = 0;;) {
-    if (c == 0) {
+    if (c == 0)
       k_japply(d, fp32, pi, ws.Q, nullptr, y, s);
-    } else {
+    else
       k_japply(d, fp32, pi, w1, eta_dev, y, s);
-      launch_form_qi(d, fp32, c, w1, s);
-    }
-    launch_dots(d, fp32, c + 1, y, false, c > 0, s);
-    launch_axpy(d, fp32, c + 1, y, w1, s);
-    launch_dots(d, fp32, c + 1, w1, true, false, s);
+    launch_gs_step(d, fp32, c, y, w1, s);
     out.bytes += B.japply(fp32) + B.gs(fp32, c);
     if (ig_status e = sync_status(d, s)) return e;
     ++out.steps;
