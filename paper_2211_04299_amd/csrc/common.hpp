@@ -18,6 +18,16 @@ struct bf16 {
   uint16_t bits;
 };
 
+// Streaming loads of transition data, which is read once per pass: the
+// non-temporal hint keeps it from displacing the reused vectors (V, x) that
+// the gathers hit in L2.
+__device__ __forceinline__ int32_t ld_stream(const int32_t* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ bf16 ld_stream(const bf16* p) {
+  return bf16{__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p))};
+}
+
 __device__ __forceinline__ double to_d(double x) { return x; }
 __device__ __forceinline__ double to_d(float x) { return (double)x; }
 __device__ __forceinline__ double to_d(bf16 x) {

@@ -15,16 +15,19 @@ constexpr int kWpb = kBlock / kWave;  // wavefronts per block
 
 template <typename VT>
 struct Vec;  // 16 bytes of stored values
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 template <>
 struct Vec<double> {
   static constexpr int N = 2;
-  using T = double2;
+  using T = d2v;
   __device__ static double at(const T& v, int k) { return k == 0 ? v.x : v.y; }
 };
 template <>
 struct Vec<float> {
   static constexpr int N = 4;
-  using T = float4;
+  using T = f4v;
   __device__ static double at(const T& v, int k) {
     return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
   }
@@ -32,13 +35,17 @@ struct Vec<float> {
 template <>
 struct Vec<bf16> {
   static constexpr int N = 8;
-  using T = uint4;
+  using T = u4v;
   __device__ static double at(const T& v, int k) {
     const unsigned w = k < 2 ? v.x : k < 4 ? v.y : k < 6 ? v.z : v.w;
     const unsigned bits = (k & 1) ? (w & 0xFFFF0000u) : (w << 16);
     return (double)__uint_as_float(bits);
   }
 };
+// 16-byte load of the row stream (a plain load: a non-temporal hint measured
+// slower on the dense rows)
+template <typename VV>
+__device__ __forceinline__ VV ldv(const VV* p) { return *p; }
 
 // sum_e row[e] * x[e] * scale over one row of length n, the whole wavefront
 // cooperating; AT is the accumulation type.  Result valid in every lane.
@@ -54,7 +61,8 @@ __device__ __forceinline__ AT dense_row_dot(const VT* __restrict__ row, int64_t 
     const int64_t nv = n / N;
     int64_t e = lane;
     for (; e + 3 * kWave < nv; e += 4 * kWave) {  // four 16-byte loads in flight per lane
-      VV p0 = rv[e], p1 = rv[e + kWave], p2 = rv[e + 2 * kWave], p3 = rv[e + 3 * kWave];
+      const VV p0 = ldv(rv + e), p1 = ldv(rv + e + kWave), p2 = ldv(rv + e + 2 * kWave),
+               p3 = ldv(rv + e + 3 * kWave);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         acc += (AT)Vec<VT>::at(p0, k) * (AT)(x[e * N + k] * scale);
@@ -64,7 +72,7 @@ __device__ __forceinline__ AT dense_row_dot(const VT* __restrict__ row, int64_t 
       }
     }
     for (; e < nv; e += kWave) {
-      VV p0 = rv[e];
+      const VV p0 = ldv(rv + e);
 #pragma unroll
       for (int k = 0; k < N; ++k) acc += (AT)Vec<VT>::at(p0, k) * (AT)(x[e * N + k] * scale);
     }

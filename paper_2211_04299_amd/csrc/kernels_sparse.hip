@@ -37,8 +37,8 @@ __device__ __forceinline__ void ell_stream(const int32_t* __restrict__ col,
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int64_t e = base + (int64_t)min(f0 + u, F - 1) * step;  // clamped: in range
-      cc[u] = col[e];
-      vv[u] = val[e];
+      cc[u] = ld_stream(col + e);
+      vv[u] = ld_stream(val + e);
     }
   };
   auto use = [&](int f0, const int32_t(&cc)[kU], const VT(&vv)[kU]) {
