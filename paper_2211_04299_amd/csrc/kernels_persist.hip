@@ -73,6 +73,7 @@ struct Lsq {
   double R[(kPMaxW + 1) * kPMaxW];  // column-major, leading dim kPMaxW+1
   double cs[kPMaxW], sn[kPMaxW], g[kPMaxW + 1], y[kPMaxW];
   double c[kPMaxW + 2], d[kPMaxW + 1];
+  double z[kPMaxW + 2];  // residual of the newest column's iterate in basis coordinates
 };
 
 struct Scal {  // per-block copies of the solver scalars (identical in every block)
@@ -81,7 +82,7 @@ struct Scal {  // per-block copies of the solver scalars (identical in every blo
       nonfinite;
 };
 
-enum : int { D_NEXT = 0, D_EXPLICIT, D_END_INNER, D_RESTART, D_CONT, D_DONE, D_NOCONV, D_ERR };
+enum : int { D_NEXT = 0, D_EXPLICIT, D_LAG, D_END_INNER, D_RESTART, D_CONT, D_DONE, D_NOCONV, D_ERR };
 
 __device__ __forceinline__ int logical_block() {
   const int nb = gridDim.x, b = blockIdx.x;
@@ -118,15 +119,15 @@ __device__ __forceinline__ bool gbarrier(unsigned int* flags, PCtl* ctl, unsigne
   return s_ok != 0;
 }
 
-// out[c] = sum (or max, maxmask bit c) over blocks of part[b][c], c < cnt;
-// fixed order; all threads; result in LDS `out`.
+// out[c] = sum (or max: maxmask bit c, or c == maxcol) over blocks of
+// part[b][c], c < cnt; fixed order; all threads; result in LDS `out`.
 __device__ void reduce_rows(const double* __restrict__ part, int cnt, unsigned maxmask,
-                            double* __restrict__ out) {
+                            double* __restrict__ out, int maxcol = -1) {
   __shared__ double seg[16][64];
   const int nb = gridDim.x;
   for (int c0 = 0; c0 < cnt; c0 += 64) {
     const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const bool mx = c0 == 0 && c < 32 && ((maxmask >> c) & 1u);
+    const bool mx = (c0 == 0 && c < 32 && ((maxmask >> c) & 1u)) || c0 + c == maxcol;
     double acc = 0.0;
     if (c0 + c < cnt)
       for (int b = q; b < nb; b += 16) {
@@ -166,6 +167,8 @@ __device__ __forceinline__ void block_reduce_big(double (&v)[NV], const int (&op
   }
 }
 
+// (kept as a plain unrolled loop: the kernel runs 1024-thread blocks, so it
+// has 128 registers per lane and a double-buffered stream would spill)
 template <typename VT, typename XT, typename AT, int G>
 __device__ __forceinline__ AT prow_dot(const SellPi<VT>& Pp, int64_t b, int l, int g,
                                        const XT* __restrict__ x) {
@@ -265,6 +268,73 @@ __device__ __forceinline__ void own_axpy(const XT* __restrict__ Q, int64_t n, in
   }
 }
 
+// Q_i = (w1 - sum_{j<i} d_j Q_j) * inv on the own rows, and the implicit
+// residual of column i-1, r = sum_{j<i} z_j Q_j + z_i Q_i, whose largest
+// |r| over the own rows is returned (valid in every thread).  Same thread
+// split as own_axpy; psum and psum2 are LDS scratch of kPB doubles each.
+template <typename XT>
+__device__ __forceinline__ double own_form(XT* __restrict__ Q, int64_t n, int64_t s_lo, int nown,
+                                           int i, const double* __restrict__ d,
+                                           const double* __restrict__ z, double inv,
+                                           const double* __restrict__ w1l, double* psum,
+                                           double* psum2) {
+  const int parts = nown >= kPB ? 1 : max(1, min(8, kPB / pow2_ceil(max(nown, 1))));
+  const int span = kPB / parts;
+  const int p = threadIdx.x / span, tl = threadIdx.x % span;
+  XT* qi = Q + (int64_t)i * n;
+  double rmax = 0.0;
+  for (int t0 = 0; t0 < nown; t0 += span) {
+    const int t = t0 + tl;
+    double ad = 0.0, az = 0.0;
+    if (t < nown) {
+      const int64_t s = s_lo + t;
+      for (int j = p; j < i; j += parts) {
+        const double q = to_d(Q[(int64_t)j * n + s]);
+        ad = fma(d[j], q, ad);
+        az = fma(z[j], q, az);
+      }
+    }
+    if (parts > 1) {
+      psum[threadIdx.x] = ad;
+      psum2[threadIdx.x] = az;
+      __syncthreads();
+      if (p == 0 && t < nown) {
+        double a = psum[tl], b = psum2[tl];
+        for (int q = 1; q < parts; ++q) {
+          a += psum[q * span + tl];
+          b += psum2[q * span + tl];
+        }
+        ad = a;
+        az = b;
+      }
+      __syncthreads();
+    }
+    if (p == 0 && t < nown) {
+      const XT qx = from_d<XT>((w1l[t] - ad) * inv);
+      qi[s_lo + t] = qx;
+      rmax = fmax(rmax, fabs(fma(z[i], to_d(qx), az)));
+    }
+  }
+  __shared__ double wm[kPWaves];
+  rmax = wave_max(rmax);
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = rmax;
+  __syncthreads();
+  double m = wm[0];
+  for (int w = 1; w < kPWaves; ++w) m = fmax(m, wm[w]);
+  __syncthreads();
+  return m;
+}
+
+// y = R^{-1} g_hat over the first `cols` columns (one thread)
+__device__ __forceinline__ void back_sub(Lsq& L, int cols) {
+  for (int j = cols - 1; j >= 0; --j) {
+    double a = L.g[j];
+    for (int l2 = j + 1; l2 < cols; ++l2) a -= L.R[l2 * (kPMaxW + 1) + j] * L.y[l2];
+    const double dj = L.R[j * (kPMaxW + 1) + j];
+    L.y[j] = dj != 0.0 ? a / dj : 0.0;
+  }
+}
+
 template <typename VT, typename XT, int G>
 __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
   using AT = XT;  // accumulation of the P^pi products inside GMRES
@@ -291,6 +361,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
   __shared__ double red[kPMaxW + 8];
   __shared__ double coef[kPMaxW + 1];
   __shared__ double psum[kPB];
+  __shared__ double psum2[kPB];
 
   if (threadIdx.x == 0) {
     sc = Scal{};
@@ -302,6 +373,46 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
 #define PARTS (A.part + (epoch & 1) * half)
   int i = 0;           // basis vectors Q_0..Q_{i-1} formed in this cycle
   bool from_r = true;  // the next basis vector is r / beta (cycle start)
+  double impl_max = 0.0;
+
+  // V = Vb + sum_{j<cols} y_j Q_j on the own rows, then the true FP64
+  // residual r = g^pi - J V with its infinity- and 2-norms into sc
+  // (two grid barriers; false if a barrier wait failed)
+  auto explicit_resid = [&](int cols) -> bool {
+    for (int j = threadIdx.x; j < cols; j += kPB) coef[j] = L.y[j];
+    __syncthreads();
+    own_axpy<XT>(A.Q, n, s_lo, nown, cols, coef, 1.0, psum, [&](int t) { return A.Vb[s_lo + t]; },
+                 [&](int t, double v) { A.V[s_lo + t] = v; });
+    if (!gbarrier(A.flags, A.ctl, ++epoch)) return false;
+    {
+      double pmax = 0.0, ps = 0.0;
+      for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
+        const int64_t s = base + ls;
+        const int64_t b = s >> 6;
+        const int l = (int)(s & 63);
+        const double acc = prow_dot<VT, double, double, G>(A.Pp, b, l, g, A.V);
+        if (s < n && g == 0) {
+          const double rr = A.cpi[s] - (A.V[s] - A.gamma * acc);
+          A.r[s] = rr;
+          pmax = fmax(pmax, fabs(rr));
+          ps = fma(rr, rr, ps);
+        }
+      }
+      double v[2] = {pmax, ps};
+      const int op[2] = {1, 0};
+      block_reduce_big<2>(v, op, MYPART);
+    }
+    if (!gbarrier(A.flags, A.ctl, ++epoch)) return false;
+    reduce_rows(PARTS, 2, 1u, red);
+    if (threadIdx.x == 0) {
+      sc.alg_bytes += A.b_resid + A.b_vec * (cols + 2.0);
+      sc.expl += 1;
+      sc.res_inf = red[0];
+      sc.res_l2sq = red[1];
+    }
+    __syncthreads();
+    return true;
+  };
 
 #define IG_BARRIER()                                    \
   do {                                                  \
@@ -322,6 +433,13 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         const int64_t ob = A.P.off[b];
         double best = INFINITY;
         int besta = A.m;
+        auto candidate = [&](int a, double q) {
+          if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;
+          if (q < best) {  // increasing a: lowest index wins ties
+            best = q;
+            besta = a;
+          }
+        };
         for (int a = g; a < A.m; a += G) {
           const int64_t bs = ob + (((int64_t)a * Kb) << 6) + l;
           double acc = 0.0;
@@ -330,12 +448,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
             const int64_t e = bs + ((int64_t)j << 6);
             acc = fma(to_d(A.P.val[e]), A.V[A.P.col[e]], acc);
           }
-          const double q = A.cost[(int64_t)a * n + sc2] + A.gamma * acc;
-          if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;
-          if (q < best) {  // increasing a: lowest index wins ties
-            best = q;
-            besta = a;
-          }
+          candidate(a, A.cost[(int64_t)a * n + sc2] + A.gamma * acc);
         }
 #pragma unroll
         for (int o = S; o < kWave; o <<= 1) {
@@ -413,11 +526,9 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
           for (int64_t s = s_lo + threadIdx.x; s < v_hi; s += kPB)
             qi[s] = from_d<XT>(A.r[s] * inv);
         } else {
-          for (int j = threadIdx.x; j < i; j += kPB) coef[j] = L.d[j];
-          __syncthreads();
-          const double inv = sc.inv_eta;
-          own_axpy<XT>(A.Q, n, s_lo, nown, i, coef, -1.0, psum, [&](int t) { return w1l[t]; },
-                       [&](int t, double v) { qi[s_lo + t] = from_d<XT>(v * inv); });
+          // second-pass correction of the previous step, applied now, and the
+          // implicit residual of column i-1 from the same basis rows
+          impl_max = own_form<XT>(A.Q, n, s_lo, nown, i, L.d, L.z, sc.inv_eta, w1l, psum, psum2);
         }
         // product: gather the complete source vector (r or w1), then scale
         const double inv_src = from_r ? 1.0 / sc.beta : sc.inv_eta;
@@ -438,10 +549,29 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         }
         __syncthreads();
         own_dots<XT>(A.Q, n, i + 1, s_lo, nown, wl, MYPART, false);
+        if (threadIdx.x == 0 && !from_r) MYPART[i + 1] = impl_max;  // reduced with max
       }
       IG_BARRIER();
-      reduce_rows(PARTS, i + 1, 0u, L.c);
+      reduce_rows(PARTS, from_r ? i + 1 : i + 2, 0u, L.c, from_r ? -1 : i + 1);
       __syncthreads();
+      if (!from_r) {
+        // the stopping test of column i-1, one step late: when the implicit
+        // residual (L.c[i+1], overwritten by the Givens update later) says it
+        // may hold, confirm on the true FP64 residual with the i columns; if
+        // it holds, step i was speculative and is dropped
+        if (threadIdx.x == 0) {
+          sc.dec = D_NEXT;
+          if (!(L.c[i + 1] > sc.thr)) {
+            back_sub(L, i);
+            sc.dec = D_LAG;
+          }
+        }
+        __syncthreads();
+        if (sc.dec == D_LAG) {
+          if (!explicit_resid(i)) goto leave;
+          if (!(sc.res_inf > sc.thr)) break;  // inner loop done
+        }
+      }
       // ---------------- [B] w1 = w - Q c; d = Q^T w1; sigma = ||w1||^2
       own_axpy<XT>(A.Q, n, s_lo, nown, i + 1, L.c, -1.0, psum, [&](int t) { return wl[t]; },
                    [&](int t, double v) {
@@ -483,6 +613,14 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         L.g[i] = cs * L.g[i];
         for (int j = 0; j <= i; ++j) L.R[i * (kPMaxW + 1) + j] = h[j];
         const double rho = fabs(L.g[i + 1]);
+        {  // residual of this column's iterate in basis coordinates
+          double v = L.g[i + 1];
+          for (int j = i; j >= 0; --j) {
+            L.z[j + 1] = L.cs[j] * v;
+            v = -L.sn[j] * v;
+          }
+          L.z[0] = v;
+        }
         sc.eta = eta;
         sc.inv_eta = eta > 0.0 ? 1.0 / eta : 0.0;
         sc.rho = rho;
@@ -495,17 +633,12 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         } else if (eta == 0.0) {
           sc.breakdowns += 1;
           dec = D_EXPLICIT;
-        } else if (!(rho > A.sqrt_n * sc.thr) || sc.steps_outer >= A.max_inner || i + 1 == A.W) {
+        } else if (!(rho > sc.thr) || sc.steps_outer >= A.max_inner || i + 1 == A.W) {
+          // ||r||_inf <= ||r||_2 = rho: the rule holds in exact arithmetic;
+          // or the cycle / step budget ends here
           dec = D_EXPLICIT;
         }
-        if (dec == D_EXPLICIT) {  // y = R^{-1} g_hat over the i+1 columns
-          for (int j = i; j >= 0; --j) {
-            double a = L.g[j];
-            for (int l2 = j + 1; l2 <= i; ++l2) a -= L.R[l2 * (kPMaxW + 1) + j] * L.y[l2];
-            const double dj = L.R[j * (kPMaxW + 1) + j];
-            L.y[j] = dj != 0.0 ? a / dj : 0.0;
-          }
-        }
+        if (dec == D_EXPLICIT) back_sub(L, i + 1);
         sc.dec = dec;
       }
       __syncthreads();
@@ -516,42 +649,14 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         continue;
       }
 
-      // ---------------- explicit test: V = Vb + Q y; r = g - J V in FP64
-      for (int j = threadIdx.x; j <= i; j += kPB) coef[j] = L.y[j];
-      __syncthreads();
-      own_axpy<XT>(A.Q, n, s_lo, nown, i + 1, coef, 1.0, psum, [&](int t) { return A.Vb[s_lo + t]; },
-                   [&](int t, double v) { A.V[s_lo + t] = v; });
-      IG_BARRIER();
-      {
-        double pmax = 0.0, psum = 0.0;
-        for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
-          const int64_t s = base + ls;
-          const int64_t b = s >> 6;
-          const int l = (int)(s & 63);
-          const double acc = prow_dot<VT, double, double, G>(A.Pp, b, l, g, A.V);
-          if (s < n && g == 0) {
-            const double rr = A.cpi[s] - (A.V[s] - A.gamma * acc);
-            A.r[s] = rr;
-            pmax = fmax(pmax, fabs(rr));
-            psum = fma(rr, rr, psum);
-          }
-        }
-        double v[2] = {pmax, psum};
-        const int op[2] = {1, 0};
-        block_reduce_big<2>(v, op, MYPART);
-      }
-      IG_BARRIER();
-      reduce_rows(PARTS, 2, 1u, red);
+      // ---------------- explicit test at i+1 columns
+      if (!explicit_resid(i + 1)) goto leave;
       if (threadIdx.x == 0) {
-        sc.alg_bytes += A.b_resid + A.b_vec * (i + 3.0);
-        sc.expl += 1;
-        sc.res_inf = red[0];
-        sc.res_l2sq = red[1];
         int dec;
-        if (sc.eta == 0.0 || red[0] <= sc.thr || sc.steps_outer >= A.max_inner) {
+        if (sc.eta == 0.0 || sc.res_inf <= sc.thr || sc.steps_outer >= A.max_inner) {
           dec = D_END_INNER;
         } else if (i + 1 == A.W) {
-          const double nb = sqrt(red[1]);
+          const double nb = sqrt(sc.res_l2sq);
           if (nb > (1.0 - 1e-6) * sc.cycle_beta) {
             sc.stagnations += 1;
             dec = D_END_INNER;
@@ -619,14 +724,15 @@ ig_status launch_persist(Mdp& d, const PArgs<VT, XT>& a, int nblocks, bool coop,
 
 // Blocks of one solve: `requested` > 0 asks for that many (clamped so that
 // a block owns at most kPMaxSpb slices); otherwise a quarter of the slices,
-// in whole XCD groups.  Depends only on the shape, the request and the CU
+// rounded to whole XCD groups (the measured optimum between per-block work
+// and grid-barrier cost for paper-scale sizes).  Depends only on the shape, the request and the CU
 // count, never on other work on the device.
 int persistent_blocks(const Mdp& d, int* spb_out, int requested = 0) {
   int want = requested > 0 ? requested
                            : (int)std::max<int64_t>(1, std::min<int64_t>(d.nslices, d.nslices / 4));
   if (requested <= 0)
     if (const char* e = std::getenv("IG_PERSIST_BLOCKS")) want = std::max(1, std::atoi(e));
-  if (requested <= 0 && want >= 16) want = want / 8 * 8;  // whole XCD groups
+  if (requested <= 0 && want >= 16) want = (want + 4) / 8 * 8;  // nearest whole XCD groups
   const int cap = std::min(kPMaxBlocks, std::max(1, d.num_cu));
   int nb = (int)std::min<int64_t>(std::min<int64_t>(d.nslices, cap), want);
   nb = std::max(nb, (int)((d.nslices + kPMaxSpb - 1) / kPMaxSpb));

@@ -18,58 +18,6 @@ namespace ig {
 
 namespace {
 
-constexpr int kU = 8;  // entries per unrolled chunk
-
-// Software-pipelined pass over F entries of one lane, entry f at
-// base + f * step: the column and value loads of chunk k+1 are issued before
-// the gathers of chunk k, so a chunk costs one memory round trip instead of
-// two.  consume(v, xs) is called per entry, in order, with the value and
-// the gathered x[col] * scale, both converted to AT.
-template <typename VT, typename XT, typename AT, typename Consume>
-__device__ __forceinline__ void ell_stream(const int32_t* __restrict__ col,
-                                           const VT* __restrict__ val, int64_t base,
-                                           int64_t step, int F, const XT* __restrict__ x,
-                                           XT scale, Consume&& consume) {
-  if (F <= 0) return;
-  int32_t c[kU], cn[kU];
-  VT v[kU], vn[kU];
-  auto load = [&](int f0, int32_t(&cc)[kU], VT(&vv)[kU]) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int64_t e = base + (int64_t)min(f0 + u, F - 1) * step;  // clamped: in range
-      cc[u] = ld_stream(col + e);
-      vv[u] = ld_stream(val + e);
-    }
-  };
-  auto use = [&](int f0, const int32_t(&cc)[kU], const VT(&vv)[kU]) {
-    XT xv[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) xv[u] = x[cc[u]];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      if (f0 + u < F) {
-        if constexpr (sizeof(AT) == 8)
-          consume(to_d(vv[u]), (AT)(xv[u] * scale));
-        else
-          consume(to_f(vv[u]), (AT)(xv[u] * scale));
-      }
-    }
-  };
-  load(0, c, v);
-  int f0 = 0;
-  for (; f0 + kU < F; f0 += 2 * kU) {
-    load(f0 + kU, cn, vn);
-    use(f0, c, v);
-    if (f0 + 2 * kU >= F) {
-      use(f0 + kU, cn, vn);
-      return;
-    }
-    load(f0 + 2 * kU, c, v);
-    use(f0 + kU, cn, vn);
-  }
-  use(f0, c, v);
-}
-
 // sum_j val[e_j] * x[col[e_j]] * scale over the entries j = g, g+G, ... < K of
 // one sliced-ELL row starting at `base` (entry j at base + (j << 6)).
 template <typename VT, typename XT, typename AT, int G>
