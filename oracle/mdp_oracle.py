@@ -39,6 +39,14 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
                            (Sec. 2.1); OPI(1) is VI.
   certificate              ||V - V*||_inf <= ||TV - V||_inf / (1 - gamma),
                            from gamma-contraction (Sec. 2).
+  action sets A(s)         every minimum runs over the admissible actions of
+                           the state (Sec. 2, problem statement): q_values
+                           gives +inf outside A(s), brute_force enumerates
+                           A(0) x ... x A(n-1).  Pinned by brute force, by a
+                           mask-free twin whose excluded actions carry a
+                           prohibitive cost (same PI trajectory), by
+                           monotonicity in the action sets and by the
+                           one-action closed form.
 
 Readings where the paper is silent or garbled (each is also listed in the
 design notes of the repository):
@@ -85,12 +93,22 @@ def _P_rows(mdp):
                          shape=(n * m, n))
 
 
+def _adm(mdp):
+    """Admissibility mask [n, m] of the action sets A(s) (Section 2), or None
+    when every action is admissible."""
+    adm = getattr(mdp, "adm", None)
+    return None if adm is None else np.asarray(adm, bool).reshape(mdp.n, mdp.m)
+
+
 def q_values(mdp, V):
     """Q[s, a] = g(s, a) + gamma * sum_s' p_ss'(a) V(s')   (the expression
-    minimised in the Bellman equation for V*, eq. 4, and in GreedyPolicy)."""
+    minimised in the Bellman equation for V*, eq. 4, and in GreedyPolicy);
+    +inf for actions outside A(s), so that every minimum runs over A(s)."""
     V = np.asarray(V, dtype=np.float64)
     EV = _P_rows(mdp) @ V
-    return (np.asarray(mdp.cost, np.float64) + mdp.gamma * EV).reshape(mdp.n, mdp.m)
+    Q = (np.asarray(mdp.cost, np.float64) + mdp.gamma * EV).reshape(mdp.n, mdp.m)
+    adm = _adm(mdp)
+    return Q if adm is None else np.where(adm, Q, np.inf)
 
 
 def bellman(mdp, V):
@@ -201,13 +219,16 @@ def value_iteration(mdp, eps=None, V0=None, max_iter=10_000_000):
 
 
 def brute_force(mdp, atol=1e-12):
-    """V* = componentwise minimum of V^pi over all m^n deterministic policies
-    (eq. 2).  Returns (V*, list of optimal policies).  Only for tiny MDPs."""
+    """V* = componentwise minimum of V^pi over all deterministic policies
+    with pi(s) in A(s) (eq. 2).  Returns (V*, list of optimal policies).
+    Only for tiny MDPs."""
     n, m = mdp.n, mdp.m
-    if m ** n > 200_000:
+    adm = _adm(mdp)
+    choices = [range(m) if adm is None else np.nonzero(adm[s])[0].tolist() for s in range(n)]
+    if np.prod([len(c) for c in choices], dtype=float) > 200_000:
         raise ValueError("too many policies for brute force")
     vals = {}
-    for pol in itertools.product(range(m), repeat=n):
+    for pol in itertools.product(*choices):
         vals[pol] = policy_eval_lu(mdp, np.array(pol, dtype=np.int32))
     Vstar = np.min(np.stack(list(vals.values())), axis=0)
     opt = [np.array(p, dtype=np.int32) for p, v in vals.items()

@@ -36,6 +36,7 @@ __all__ = [
     "MDP", "sparse_uniform", "sparse_band", "dense_exp", "config", "CONFIGS",
     "round_values", "upcast_values", "serving_stream", "ServingRequest",
     "from_rows", "self_loops", "uniform_transitions", "cyclic", "random_micro",
+    "with_action_sets",
 ]
 
 
@@ -46,6 +47,9 @@ class MDP:
     fmt == "csr":   row_ptr int64[n*m+1], col int32[nnz], val float64[nnz]
     fmt == "dense": P float64[n, m, n]   (P[s, a, s'])
     cost float64[n*m] with cost[s*m + a] = g(s, a).
+    adm (optional) bool[n*m]: adm[s*m + a] says whether action a is
+    admissible in state s (the action set A(s)); None = every action.  Rows
+    and costs of inadmissible pairs carry no meaning (CSR rows may be empty).
     """
     n: int
     m: int
@@ -58,6 +62,7 @@ class MDP:
     P: Optional[np.ndarray] = None
     name: str = ""
     meta: dict = field(default_factory=dict)
+    adm: Optional[np.ndarray] = None
 
     @property
     def nnz(self) -> int:
@@ -69,7 +74,7 @@ class MDP:
         """Same MDP structure with replaced probability values."""
         return MDP(self.n, self.m, self.gamma, self.cost, self.fmt, self.row_ptr,
                    self.col, val if val is not None else self.val,
-                   P if P is not None else self.P, self.name, dict(self.meta))
+                   P if P is not None else self.P, self.name, dict(self.meta), self.adm)
 
 
 # ---------------------------------------------------------------------------
@@ -325,6 +330,34 @@ def config(name: str, seed: int = 0, n: Optional[int] = None, gamma: Optional[fl
     mdp.name = f"{name}-seed{seed}"
     mdp.meta["restart"] = c["restart"]
     return mdp
+
+
+def with_action_sets(mdp: MDP, keep: float, seed: int, empty_rows: bool = True,
+                     nan_costs: bool = True) -> MDP:
+    """State-dependent action sets: each (s, a) is admissible with
+    probability `keep` (at least one action per state, drawn uniformly when
+    none survives).  With empty_rows (CSR) the rows of inadmissible pairs are
+    dropped from the CSR arrays; with nan_costs their costs become NaN --
+    both must be ignored by every consumer."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0xAC7]))
+    n, m = mdp.n, mdp.m
+    adm = rng.random((n, m)) < keep
+    none = ~adm.any(axis=1)
+    adm[np.nonzero(none)[0], rng.integers(0, m, size=int(none.sum()))] = True
+    adm = adm.reshape(-1)
+    cost = np.asarray(mdp.cost, np.float64).copy()
+    if nan_costs:
+        cost[~adm] = np.nan
+    out = MDP(n, m, mdp.gamma, cost, mdp.fmt, mdp.row_ptr, mdp.col, mdp.val, mdp.P,
+              (mdp.name or "mdp") + f"-A{keep:g}", dict(mdp.meta), adm)
+    if mdp.fmt == "csr" and empty_rows:
+        lens = np.diff(mdp.row_ptr)
+        keep_e = np.repeat(adm, lens)
+        out.col = np.ascontiguousarray(mdp.col[keep_e])
+        out.val = np.ascontiguousarray(np.asarray(mdp.val)[keep_e])
+        out.row_ptr = np.concatenate([[0], np.cumsum(np.where(adm, lens, 0))]).astype(np.int64)
+    out.meta["action_keep"] = keep
+    return out
 
 
 @dataclass

@@ -272,3 +272,98 @@ def test_certificate_bounds_error(small):
     for scale in (1e-2, 1e-5, 1e-9):
         V = Vs + scale * rng.normal(size=small.n)
         assert np.max(np.abs(V - Vs)) <= O.certificate(small, V) * (1 + 1e-9) + 1e-15
+
+
+# ---- state-dependent action sets A(s) (Section 2) --------------------------
+
+def _masked(base, keep, seed, **kw):
+    return synth.with_action_sets(base, keep, seed, **kw)
+
+
+def _penalty_twin(base, adm):
+    """The same MDP without a mask, every inadmissible action given a cost no
+    optimal or greedy choice can afford: c_pen = 10 max|c| / (1 - gamma) + 1."""
+    cost = np.asarray(base.cost, np.float64).copy()
+    big = 10.0 * np.max(np.abs(cost)) / (1.0 - base.gamma) + 1.0
+    cost[~adm] = big
+    return synth.MDP(base.n, base.m, base.gamma, cost, base.fmt, base.row_ptr, base.col,
+                     base.val, base.P, base.name + "-pen", dict(base.meta))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_action_sets_brute_force_matches_pi(seed):
+    mdp = _masked(synth.random_micro(4, 3, 0.9, seed), 0.5, seed)
+    adm = mdp.adm.reshape(mdp.n, mdp.m)
+    Vb, opts = O.brute_force(mdp)
+    Vp, pip, _ = O.policy_iteration(mdp)
+    assert np.allclose(Vp, Vb, rtol=1e-10, atol=1e-12)
+    assert any(np.array_equal(pip, o) for o in opts)
+    assert adm[np.arange(mdp.n), pip].all()
+    # every optimal policy found by enumeration is admissible
+    assert all(adm[np.arange(mdp.n), o].all() for o in opts)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_action_sets_equal_prohibitive_costs(seed):
+    """A mask (with the rows and costs of inadmissible pairs removed or NaN)
+    and a mask-free twin whose inadmissible actions cost too much to be
+    chosen give the same PI trajectory, hence the same V* and pi*."""
+    base = synth.config("c1", seed)
+    mdp = _masked(base, 0.6, 7 + seed)
+    twin = _penalty_twin(base, mdp.adm)
+    V1, pi1, it1 = O.policy_iteration(mdp)
+    V2, pi2, it2 = O.policy_iteration(twin)
+    assert it1 == it2
+    assert np.array_equal(pi1, pi2)
+    assert np.allclose(V1, V2, rtol=1e-12, atol=0)
+    Vv, _ = O.value_iteration(mdp)
+    assert np.allclose(Vv, V1, rtol=1e-9)
+
+
+def test_action_sets_restriction_raises_values():
+    """Minimising over a subset of actions can only raise V* (eq. 2)."""
+    base = synth.config("c1", 3)
+    Vf, _, _ = O.policy_iteration(base)
+    for keep in (0.8, 0.5, 0.3):
+        Vm, _, _ = O.policy_iteration(_masked(base, keep, 11))
+        assert np.all(Vm >= Vf - 1e-12 * np.max(np.abs(Vf)))
+
+
+def test_action_sets_single_action_states():
+    """A state with one admissible action a: pi*(s) = a and V*(s) solves the
+    Bellman equation with that action alone."""
+    base = synth.config("c1", 4)
+    mdp = _masked(base, 0.35, 5)
+    adm = mdp.adm.reshape(mdp.n, mdp.m)
+    V, pi, _ = O.policy_iteration(mdp)
+    single = np.nonzero(adm.sum(axis=1) == 1)[0]
+    assert single.size > 0
+    a = np.argmax(adm[single], axis=1)
+    assert np.array_equal(pi[single], a)
+    rows = O._P_rows(base)[single * mdp.m + a]
+    rhs = base.cost.reshape(mdp.n, mdp.m)[single, a] + mdp.gamma * (rows @ V)
+    assert np.allclose(V[single], rhs, rtol=1e-12)
+
+
+def test_action_sets_full_mask_is_plain():
+    base = synth.config("c1", 1)
+    full = synth.MDP(base.n, base.m, base.gamma, base.cost, base.fmt, base.row_ptr, base.col,
+                     base.val, base.P, "full", dict(base.meta), np.ones(base.n * base.m, bool))
+    V1, pi1, _ = O.policy_iteration(base)
+    V2, pi2, _ = O.policy_iteration(full)
+    assert np.array_equal(pi1, pi2) and np.array_equal(V1, V2)
+    TV1, p1, r1 = O.bellman(base, V1)
+    TV2, p2, r2 = O.bellman(full, V1)
+    assert np.array_equal(TV1, TV2) and np.array_equal(p1, p2)
+
+
+def test_action_sets_igmres_pi_reaches_masked_optimum():
+    base = synth.config("c1", 2)
+    mdp = _masked(base, 0.5, 3)
+    Vs, pis, _ = O.policy_iteration(mdp)
+    V, pi, st = O.igmres_pi(mdp, W=20, tol=1e-11)
+    assert st.converged
+    assert np.max(np.abs(V - Vs)) <= 1e-9 * np.max(np.abs(Vs))
+    gaps = O.action_gaps(mdp, Vs)
+    sel = gaps > 1e-9
+    assert np.array_equal(pi[sel], pis[sel])
