@@ -68,10 +68,12 @@ typedef enum { IG_MODE_FP64 = 0, IG_MODE_MIXED = 1 } ig_mode;
  * bit patterns, uint16).  store is the type P is kept in on the device; it
  * may be narrower than val_type (conversion rounds to nearest even, through
  * fp32 for bf16) but not wider.
- * Validation (when `validate` != 0): 0 <= P <= 1; no column repeated inside
- * a row; every row sums to 1 within 1e-10 (FP64 input) or 1/64 (FP32 or BF16
- * input), and gamma * (largest stored row sum) < 1.  Always checked: sizes,
- * row_ptr, column range, non-empty rows, finite costs. */
+ * Validation (when `validate` != 0), over admissible pairs: 0 <= P <= 1;
+ * no column repeated inside a row; every row sums to 1 within 1e-10 (FP64
+ * input) or 1/64 (FP32 or BF16 input), and gamma * (largest stored row sum)
+ * < 1.  Always checked: sizes, row_ptr (nondecreasing), column range and
+ * non-empty rows of admissible pairs, finite costs of admissible pairs, a
+ * nonempty A(s) for every state. */
 typedef struct {
   int64_t n;
   int32_t m;
@@ -83,8 +85,17 @@ typedef struct {
   ig_dtype val_type;
   const double* cost;      /* n*m */
   ig_dtype store;
-  int32_t inputs_on_device;/* 1: row_ptr, col, val, cost are device pointers */
+  int32_t inputs_on_device;/* 1: row_ptr, col, val, cost, admissible are
+                              device pointers                                 */
   int32_t validate;
+  const uint8_t* admissible;/* NULL: every action is admissible in every
+                              state.  Else n*m bytes, admissible[s*m + a] != 0
+                              iff a is in A(s), the action set of s (Section
+                              2); every state needs one.  Costs and CSR rows
+                              of excluded pairs are ignored (the rows may be
+                              empty); the Bellman operator, greedy policies
+                              and every solver minimise over A(s) only, and
+                              policies passed in must lie in A(s).            */
 } ig_mdp_desc;
 
 /* Solver parameters.  Algorithm 2's inputs are V0 (the V argument), alpha,

@@ -66,6 +66,8 @@ struct SellP {
   const VT* __restrict__ val;
   const int64_t* __restrict__ off;   // [nslices]
   const int32_t* __restrict__ width; // [nslices]
+  const int32_t* __restrict__ mcnt;  // [nslices] action blocks stored for the slice
+  const uint8_t* __restrict__ adm;   // [m][n] admissibility, or null (all admissible)
 };
 
 template <typename VT>

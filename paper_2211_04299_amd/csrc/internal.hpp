@@ -78,6 +78,7 @@ struct Mdp {
   void* val = nullptr;
   int64_t* off = nullptr;
   int32_t* width = nullptr;
+  int32_t* mcnt = nullptr;  // action blocks stored per slice (1 + largest admissible action)
   int64_t* offp = nullptr;
   int32_t* pcol = nullptr;  // compact P^pi
   void* pval = nullptr;
@@ -86,7 +87,8 @@ struct Mdp {
   // dense input: P[s][a][s'] row-major
   void* P = nullptr;
 
-  double* cost = nullptr;  // [m][n] (transposed)
+  uint8_t* adm = nullptr;  // [m][n] admissibility (null: all actions admissible)
+  double* cost = nullptr;  // [m][n] (transposed; 0 for excluded pairs)
   double* cpi = nullptr;   // g^pi
 
   DevStatus* st = nullptr;      // device

@@ -95,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense(
     const VT* __restrict__ P, const double* __restrict__ cost, int m, int64_t n, double gamma,
     const double* __restrict__ V, double* __restrict__ TV, double* __restrict__ Phi,
     int32_t* __restrict__ pi, const int32_t* __restrict__ pi_old, double tie_abs,
-    double* __restrict__ cpi, double* __restrict__ part, bool vec_ok) {
+    double* __restrict__ cpi, double* __restrict__ part, bool vec_ok,
+    const uint8_t* __restrict__ adm) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   __shared__ double sb[kWpb], sq[kWpb];
   __shared__ int sa[kWpb];
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense(
     double best = INFINITY, qinc = INFINITY;
     int besta = m;
     for (int a = wid; a < m; a += kWpb) {
+      if (adm && !adm[(int64_t)a * n + s]) continue;  // a is not in A(s)
       const double acc = dense_row_dot<VT, double, double>(P + ((int64_t)s * m + a) * n, n, V, 1.0,
                                                            lane, vec_ok);
       const double q = cost[(int64_t)a * n + s] + gamma * acc;
@@ -214,13 +216,14 @@ __global__ __launch_bounds__(kBlock) void k_policy_pass_dense(
 
 __global__ __launch_bounds__(kBlock) void k_gather_dense(const double* __restrict__ cost, int m,
                                                          int64_t n, const int32_t* __restrict__ pi,
+                                                         const uint8_t* __restrict__ adm,
                                                          double* __restrict__ cpi,
                                                          double* __restrict__ part) {
   double bad = 0.0;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * kBlock) {
     int a = pi[s];
-    if (a < 0 || a >= m) {
+    if (a < 0 || a >= m || (adm && !adm[(int64_t)a * n + s])) {  // not in A(s)
       bad += 1.0;
       a = 0;
     }
@@ -262,7 +265,7 @@ void launch_bellman_dense(Mdp& d, const double* V, double* TV, double* Phi, int3
       using VT = decltype(t);
       hipLaunchKernelGGL(k_bellman_dense<VT>, dim3(grid_states(d.n)), dim3(kBlock), 0, s,
                          (const VT*)d.P, (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi,
-                         pi_old, tie_abs, d.cpi, d.part, vec_ok(d));
+                         pi_old, tie_abs, d.cpi, d.part, vec_ok(d), (const uint8_t*)d.adm);
     });
   }
   launch_finalize(d, FIN_BELLMAN, grid_states(d.n), s);
@@ -315,7 +318,7 @@ void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s) {
   {
     ProfScope p(d, KC_OTHER, s);
     hipLaunchKernelGGL(k_gather_dense, dim3(grid_threads(d.n)), dim3(kBlock), 0, s,
-                       (const double*)d.cost, d.m, d.n, pi, d.cpi, d.part);
+                       (const double*)d.cost, d.m, d.n, pi, (const uint8_t*)d.adm, d.cpi, d.part);
   }
   launch_finalize(d, FIN_GATHER, grid_threads(d.n), s);
 }

@@ -429,18 +429,19 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         const int64_t sc2 = valid ? s : n - 1;
         const int64_t b = s >> 6;
         const int l = (int)(s & 63);
-        const int Kb = A.P.width[b];
+        const int Kb = A.P.width[b], Mb = A.P.mcnt[b];
         const int64_t ob = A.P.off[b];
         double best = INFINITY;
         int besta = A.m;
         auto candidate = [&](int a, double q) {
+          if (A.P.adm && !A.P.adm[(int64_t)a * n + sc2]) return;  // a is not in A(s)
           if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;
           if (q < best) {  // increasing a: lowest index wins ties
             best = q;
             besta = a;
           }
         };
-        for (int a = g; a < A.m; a += G) {
+        for (int a = g; a < Mb; a += G) {
           const int64_t bs = ob + (((int64_t)a * Kb) << 6) + l;
           double acc = 0.0;
 #pragma unroll 8
@@ -748,7 +749,7 @@ ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coo
   int spb = 0;
   const int nb = persistent_blocks(d, &spb, p.blocks);
   PArgs<VT, XT> a;
-  a.P = SellP<VT>{d.col, (const VT*)d.val, d.off, d.width};
+  a.P = SellP<VT>{d.col, (const VT*)d.val, d.off, d.width, d.mcnt, d.adm};
   a.Pp = SellPi<VT>{d.pcol, (VT*)d.pval, d.offp, d.width};
   a.cost = d.cost;
   a.m = d.m;

@@ -64,13 +64,14 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
     const int64_t sc = valid ? s : n - 1;
     const int64_t b = s >> 6;
     const int l = (int)(s & 63);
-    const int Kb = P.width[b];
+    const int Kb = P.width[b], Mb = P.mcnt[b];
     const int64_t ob = P.off[b] + l;
     const int inc = pi_old ? pi_old[sc] : -1;
 
     double best = INFINITY, qinc = INFINITY;
     int besta = m;  // sentinel: no finite candidate yet
     auto candidate = [&](int a, double q) {
+      if (P.adm && !P.adm[(int64_t)a * n + sc]) return;  // a is not in A(s)
       if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;  // NaN or +-Inf
       if (q < best) {  // actions visited in increasing order: lowest index wins ties
         best = q;
@@ -84,18 +85,18 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
       // loaded when the row starts and used when it ends
       double acc = 0.0, cst = cost[sc];
       int j = 0, a = 0;
-      ell_stream<VT, double, double>(P.col, P.val, ob, kSlice, m * Kb, V, 1.0,
+      ell_stream<VT, double, double>(P.col, P.val, ob, kSlice, Mb * Kb, V, 1.0,
                                      [&](double pv, double xv) {
                                        acc = fma(pv, xv, acc);
                                        if (++j == Kb) {
                                          candidate(a, cst + gamma * acc);
                                          acc = 0.0;
                                          j = 0;
-                                         if (++a < m) cst = cost[(int64_t)a * n + sc];
+                                         if (++a < Mb) cst = cost[(int64_t)a * n + sc];
                                        }
                                      });
     } else {
-      for (int a = g; a < m; a += G) {
+      for (int a = g; a < Mb; a += G) {
         const double acc = ell_row<VT, double, double, 1>(
             P.col, P.val, ob + (((int64_t)a * Kb) << 6), Kb, 0, V, 1.0);
         candidate(a, cost[(int64_t)a * n + sc] + gamma * acc);
@@ -231,12 +232,12 @@ __global__ __launch_bounds__(kBlock) void k_gather_policy(SellP<VT> P, SellPi<VT
     const bool valid = s < n;
     const int64_t b = s >> 6;
     const int l = (int)(s & 63);
+    const int Kb = P.width[b], Mb = P.mcnt[b];
     int a = valid ? pi[s] : 0;
-    if (a < 0 || a >= m) {
-      if (g == 0) bad += 1.0;
-      a = 0;
+    if (a < 0 || a >= Mb || (valid && P.adm && !P.adm[(int64_t)a * n + s])) {  // not in A(s)
+      if (g == 0 && valid) bad += 1.0;
+      a = 0;  // a stored block (zero padding when excluded): stays in bounds
     }
-    const int Kb = P.width[b];
     const int64_t src = P.off[b] + (((int64_t)a * Kb) << 6) + l;
     const int64_t dst = Pp.off[b] + l;
     for (int j = g; j < Kb; j += G) {
@@ -258,7 +259,7 @@ inline int grid_for(const Mdp& d, int G) {
 
 template <typename VT>
 SellP<VT> viewP(Mdp& d) {
-  return SellP<VT>{d.col, (const VT*)d.val, d.off, d.width};
+  return SellP<VT>{d.col, (const VT*)d.val, d.off, d.width, d.mcnt, d.adm};
 }
 template <typename VT>
 SellPi<VT> viewPi(Mdp& d) {

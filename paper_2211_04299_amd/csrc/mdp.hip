@@ -157,12 +157,14 @@ struct FillOut {
 };
 
 // Sliced-ELL image of a CSR MDP: entry (a, j, lane) of slice b at
-// off[b] + ((a*K_b + j) << 6) + lane; padding (j >= row length, lanes past
-// n) is written as column 0, probability 0.  Every entry is written once.
+// off[b] + ((a*K_b + j) << 6) + lane for a < M_b (the slice's action
+// blocks); padding (j >= row length, excluded pairs, lanes past n) is
+// written as column 0, probability 0.  Every entry is written once; checks
+// run over admissible pairs only.
 template <typename IN, typename OUT>
 FillOut fill_sell(int64_t n, int m, const int64_t* rp, const int32_t* col, const IN* val,
-                  const int32_t* width, const int64_t* off, int32_t* scol, OUT* sval, bool validate,
-                  double sum_tol) {
+                  const int32_t* width, const int32_t* mcnt, const int64_t* off,
+                  const uint8_t* adm, int32_t* scol, OUT* sval, bool validate, double sum_tol) {
   const int64_t ns = (n + kSlice - 1) / kSlice;
   FillOut F;
   int bad_col = 0, bad_dup = 0, bad_p = 0, bad_sum = 0;
@@ -174,14 +176,15 @@ FillOut fill_sell(int64_t n, int m, const int64_t* rp, const int32_t* col, const
     uint32_t rid = 0;
 #pragma omp for schedule(dynamic, 4)
     for (int64_t b = 0; b < ns; ++b) {
-      const int Kb = width[b];
+      const int Kb = width[b], Mb = mcnt[b];
       const int64_t ob = off[b];
       for (int l = 0; l < kSlice; ++l) {
         const int64_t s = b * kSlice + l;
-        for (int a = 0; a < m; ++a) {
+        for (int a = 0; a < Mb; ++a) {
           const int64_t base = ob + (((int64_t)a * Kb) << 6) + l;
+          const bool use = s < n && (!adm || adm[s * m + a]);
           int64_t lo = 0, len = 0;
-          if (s < n) {
+          if (use) {
             lo = rp[s * m + a];
             len = rp[s * m + a + 1] - lo;
           }
@@ -212,7 +215,7 @@ FillOut fill_sell(int64_t n, int m, const int64_t* rp, const int32_t* col, const
             scol[pos] = 0;
             VT_<OUT>::out(0.0, &sval[pos]);
           }
-          if (s < n) {
+          if (use) {
             if (validate && !(std::fabs(sum - 1.0) <= sum_tol)) ++bad_sum;
             mss = std::max(mss, ssum);
           }
@@ -230,13 +233,20 @@ FillOut fill_sell(int64_t n, int m, const int64_t* rp, const int32_t* col, const
 
 template <typename IN>
 FillOut fill_sell_in(ig_dtype store, int64_t n, int m, const int64_t* rp, const int32_t* col,
-                     const void* val, const int32_t* width, const int64_t* off, int32_t* scol,
-                     void* sval, bool validate, double sum_tol) {
+                     const void* val, const int32_t* width, const int32_t* mcnt,
+                     const int64_t* off, const uint8_t* adm, int32_t* scol, void* sval,
+                     bool validate, double sum_tol) {
   const IN* v = (const IN*)val;
   switch (store) {
-    case IG_FP64: return fill_sell<IN, double>(n, m, rp, col, v, width, off, scol, (double*)sval, validate, sum_tol);
-    case IG_FP32: return fill_sell<IN, float>(n, m, rp, col, v, width, off, scol, (float*)sval, validate, sum_tol);
-    default: return fill_sell<IN, uint16_t>(n, m, rp, col, v, width, off, scol, (uint16_t*)sval, validate, sum_tol);
+    case IG_FP64:
+      return fill_sell<IN, double>(n, m, rp, col, v, width, mcnt, off, adm, scol, (double*)sval,
+                                   validate, sum_tol);
+    case IG_FP32:
+      return fill_sell<IN, float>(n, m, rp, col, v, width, mcnt, off, adm, scol, (float*)sval,
+                                  validate, sum_tol);
+    default:
+      return fill_sell<IN, uint16_t>(n, m, rp, col, v, width, mcnt, off, adm, scol,
+                                     (uint16_t*)sval, validate, sum_tol);
   }
 }
 
@@ -250,7 +260,8 @@ void free_all(Mdp* d) {
   auto F = [dev](void* p) {
     if (p && dev) (void)hipFree(p);
   };
-  F(d->col); F(d->val); F(d->off); F(d->width); F(d->offp); F(d->pcol); F(d->pval);
+  F(d->col); F(d->val); F(d->off); F(d->width); F(d->mcnt); F(d->offp); F(d->pcol); F(d->pval);
+  F(d->adm);
   F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->pctl);
   F(d->ws.Q); F(d->ws.wA); F(d->ws.wB); F(d->ws.Vb); F(d->ws.r); F(d->ws.t); F(d->ws.pi);
   if (d->own_host_mirrors) {
@@ -354,6 +365,23 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
   std::vector<double> cost_h = to_host(desc->cost, (size_t)R, ondev, &st);
   if (st) return st;
   const double* cost = ondev ? cost_h.data() : desc->cost;
+  // action sets A(s): admissibility mask [s][a] (null: every action)
+  std::vector<uint8_t> adm_h;
+  const uint8_t* adm = nullptr;
+  if (desc->admissible) {
+    adm_h = to_host(desc->admissible, (size_t)R, ondev, &st);
+    if (st) return st;
+    adm = ondev ? adm_h.data() : desc->admissible;
+    int64_t empty = 0;
+#pragma omp parallel for reduction(+ : empty)
+    for (int64_t s = 0; s < n; ++s) {
+      bool any = false;
+      for (int a = 0; a < m; ++a) any = any || adm[s * m + a] != 0;
+      empty += !any;
+    }
+    if (empty) return fail(IG_E_INVALID, "every state needs at least one admissible action");
+  }
+  auto admissible = [adm, m](int64_t s, int a) { return !adm || adm[s * m + a] != 0; };
   const double sum_tol = desc->val_type == IG_FP64 ? 1e-10 : 1.0 / 64.0;
   const bool validate = desc->validate != 0;
 
@@ -379,15 +407,29 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
 #pragma omp parallel for reduction(+ : bad_cost) reduction(max : cmax)
     for (int64_t s = 0; s < n; ++s)
       for (int a = 0; a < m; ++a) {
+        if (!admissible(s, a)) {  // ignored: a neutral value on the device
+          cost_t[(size_t)a * n + s] = 0.0;
+          continue;
+        }
         const double c = cost[s * m + a];
         if (!std::isfinite(c)) ++bad_cost;
         else cmax = std::max(cmax, std::fabs(c));
         cost_t[(size_t)a * n + s] = c;
       }
-    if (bad_cost) return fail(IG_E_INVALID, "costs must be finite");
+    if (bad_cost) return fail(IG_E_INVALID, "costs of admissible pairs must be finite");
     d->cost_max = cmax;
     return IG_OK;
   };
+
+  uint8_t* adm_t = nullptr;  // [m][n] on the host staging
+  auto transpose_adm = [&]() {
+    if (!adm) return;
+    adm_t = hs.take<uint8_t>((size_t)R);
+#pragma omp parallel for
+    for (int64_t s = 0; s < n; ++s)
+      for (int a = 0; a < m; ++a) adm_t[(size_t)a * n + s] = adm[s * m + a] != 0;
+  };
+  const size_t adm_bytes = adm ? Staging::round64((size_t)R) : 0;
 
   if (desc->fmt == IG_FMT_CSR) {
     std::vector<int64_t> rp_h = to_host(desc->row_ptr, (size_t)R + 1, ondev, &st);
@@ -397,8 +439,9 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     int bad_rows = 0;
 #pragma omp parallel for reduction(+ : bad_rows)
     for (int64_t r = 0; r < R; ++r)
-      if (rp[r + 1] <= rp[r]) ++bad_rows;
-    if (bad_rows) return fail(IG_E_INVALID, "every (s,a) row must be non-empty and row_ptr increasing");
+      if (rp[r + 1] < rp[r] || (rp[r + 1] == rp[r] && admissible(r / m, (int)(r % m)))) ++bad_rows;
+    if (bad_rows)
+      return fail(IG_E_INVALID, "row_ptr must be nondecreasing and every admissible (s,a) row non-empty");
     const int64_t nnz = rp[R];
     std::vector<int32_t> col_h = to_host(desc->col, (size_t)nnz, ondev, &st);
     if (st) return st;
@@ -412,51 +455,64 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       valp = val_h.data();
     }
 
-    // widths per 64-state slice
+    // per 64-state slice: width (longest admissible row) and action blocks
+    // (1 + largest admissible action index of its states)
     const int64_t ns = (n + kSlice - 1) / kSlice;
-    std::vector<int32_t> width((size_t)ns, 0);
+    std::vector<int32_t> width((size_t)ns, 0), mblk((size_t)ns, 0);
     int64_t maxlen = 0;
 #pragma omp parallel for reduction(max : maxlen)
     for (int64_t b = 0; b < ns; ++b) {
       int64_t w = 0;
+      int mb = 0;
       for (int64_t s = b * kSlice; s < std::min(n, (b + 1) * kSlice); ++s)
-        for (int a = 0; a < m; ++a) w = std::max(w, rp[s * m + a + 1] - rp[s * m + a]);
+        for (int a = 0; a < m; ++a)
+          if (admissible(s, a)) {
+            w = std::max(w, rp[s * m + a + 1] - rp[s * m + a]);
+            mb = std::max(mb, a + 1);
+          }
       width[b] = (int32_t)w;
+      mblk[b] = mb;
       maxlen = std::max(maxlen, w);
     }
     if (maxlen > n) return fail(IG_E_INVALID, "a row has more entries than states");
     int64_t tot = 0, totp = 0;
     for (int64_t b = 0; b < ns; ++b) {
-      tot += (int64_t)m * width[b] * kSlice;
+      tot += (int64_t)mblk[b] * width[b] * kSlice;
       totp += (int64_t)width[b] * kSlice;
     }
     const size_t need = Staging::round64((size_t)R * 8) + Staging::round64((size_t)tot * 4) +
                         Staging::round64((size_t)tot * d->vb) + 2 * Staging::round64((size_t)ns * 8) +
-                        Staging::round64((size_t)ns * 4);
+                        2 * Staging::round64((size_t)ns * 4) + adm_bytes;
     if (ig_status e = stage_get(need)) return e;
     if (ig_status e = transpose_costs()) return e;
+    transpose_adm();
     int64_t* off = hs.take<int64_t>((size_t)ns);
     int64_t* offp = hs.take<int64_t>((size_t)ns);
     int32_t* wid = hs.take<int32_t>((size_t)ns);
+    int32_t* mc = hs.take<int32_t>((size_t)ns);
     int32_t* scol = hs.take<int32_t>((size_t)tot);
     void* sval = hs.take<char>((size_t)tot * d->vb);
     for (int64_t b = 0, t = 0, tp = 0; b < ns; ++b) {
       off[b] = t;
       offp[b] = tp;
       wid[b] = width[b];
-      t += (int64_t)m * width[b] * kSlice;
+      mc[b] = mblk[b];
+      t += (int64_t)mblk[b] * width[b] * kSlice;
       tp += (int64_t)width[b] * kSlice;
     }
     FillOut F;
     switch (desc->val_type) {
       case IG_FP64:
-        F = fill_sell_in<double>(d->store, n, m, rp, col, valp, wid, off, scol, sval, validate, sum_tol);
+        F = fill_sell_in<double>(d->store, n, m, rp, col, valp, wid, mc, off, adm, scol, sval, validate,
+                                 sum_tol);
         break;
       case IG_FP32:
-        F = fill_sell_in<float>(d->store, n, m, rp, col, valp, wid, off, scol, sval, validate, sum_tol);
+        F = fill_sell_in<float>(d->store, n, m, rp, col, valp, wid, mc, off, adm, scol, sval, validate,
+                                 sum_tol);
         break;
       default:
-        F = fill_sell_in<uint16_t>(d->store, n, m, rp, col, valp, wid, off, scol, sval, validate, sum_tol);
+        F = fill_sell_in<uint16_t>(d->store, n, m, rp, col, valp, wid, mc, off, adm, scol, sval, validate,
+                                 sum_tol);
         break;
     }
     if (F.bad_col) return fail(IG_E_INVALID, "column index out of range");
@@ -474,14 +530,15 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     d->h_width = width;
     if (dmalloc(&d->col, (size_t)tot * 4) || dmalloc(&d->val, (size_t)tot * d->vb) ||
         dmalloc(&d->off, (size_t)ns * 8) || dmalloc(&d->offp, (size_t)ns * 8) ||
-        dmalloc(&d->width, (size_t)ns * 4) || dmalloc(&d->pcol, (size_t)totp * 4) ||
-        dmalloc(&d->pval, (size_t)totp * d->vb))
+        dmalloc(&d->width, (size_t)ns * 4) || dmalloc(&d->mcnt, (size_t)ns * 4) ||
+        dmalloc(&d->pcol, (size_t)totp * 4) || dmalloc(&d->pval, (size_t)totp * d->vb))
       return IG_E_NOMEM;
     if (ig_status e = upload(d, d->col, scol, (size_t)tot * 4)) return e;
     if (ig_status e = upload(d, d->val, sval, (size_t)tot * d->vb)) return e;
     if (ig_status e = upload(d, d->off, off, (size_t)ns * 8)) return e;
     if (ig_status e = upload(d, d->offp, offp, (size_t)ns * 8)) return e;
     if (ig_status e = upload(d, d->width, wid, (size_t)ns * 4)) return e;
+    if (ig_status e = upload(d, d->mcnt, mc, (size_t)ns * 4)) return e;
     if (ig_status e = dzero(d, d->pcol, (size_t)totp * 4)) return e;
     if (ig_status e = dzero(d, d->pval, (size_t)totp * d->vb)) return e;
 
@@ -501,22 +558,25 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       valp = val_h.data();
     }
     const ValReader rv{valp, desc->val_type};
-    if (ig_status e = stage_get(Staging::round64((size_t)R * 8) + Staging::round64((size_t)total * d->vb)))
+    if (ig_status e = stage_get(Staging::round64((size_t)R * 8) +
+                                Staging::round64((size_t)total * d->vb) + adm_bytes))
       return e;
     if (ig_status e = transpose_costs()) return e;
+    transpose_adm();
     uint8_t* sval = hs.take<uint8_t>((size_t)total * d->vb);
     int bad_p = 0, bad_sum = 0;
     double max_stored_sum = 0.0;
 #pragma omp parallel for reduction(+ : bad_p, bad_sum) reduction(max : max_stored_sum) schedule(dynamic, 64)
     for (int64_t r = 0; r < R; ++r) {
+      const bool use = admissible(r / m, (int)(r % m));
       double sum = 0.0, ssum = 0.0;
       for (int64_t e = r * n; e < (r + 1) * n; ++e) {
-        const double p = rv(e);
+        const double p = use ? rv(e) : 0.0;  // excluded rows: stored as zeros
         if (validate && !(p >= 0.0 && p <= 1.0)) ++bad_p;
         sum += p;
         ssum += store_val(sval, e, d->store, p);
       }
-      if (validate && !(std::fabs(sum - 1.0) <= sum_tol)) ++bad_sum;
+      if (use && validate && !(std::fabs(sum - 1.0) <= sum_tol)) ++bad_sum;
       max_stored_sum = std::max(max_stored_sum, ssum);
     }
     if (bad_p) return fail(IG_E_INVALID, "probabilities must lie in [0,1]");
@@ -536,6 +596,10 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       dmalloc(&d->pctl, sizeof(PCtl)))
     return IG_E_NOMEM;
   if (ig_status e = upload(d, d->cost, cost_t, (size_t)R * 8)) return e;
+  if (adm_t) {
+    if (dmalloc(&d->adm, (size_t)R)) return IG_E_NOMEM;
+    if (ig_status e = upload(d, d->adm, adm_t, (size_t)R)) return e;
+  }
   if (ig_status e = dzero(d, d->st, sizeof(DevStatus))) return e;
   if (ig_status e = dzero(d, d->gs, sizeof(GivensState))) return e;
   if (d->own_host_mirrors &&
@@ -623,20 +687,28 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
   if (desc->fmt == IG_FMT_CSR) {
     if (desc->inputs_on_device) return fail(IG_E_INVALID, "footprint needs host CSR arrays");
     const int64_t* rp = desc->row_ptr;
+    const uint8_t* adm = desc->admissible;
+    const int m = desc->m;
     const int64_t ns = (n + kSlice - 1) / kSlice;
     int64_t tot = 0, totp = 0;
     for (int64_t sl = 0; sl < ns; ++sl) {
       int64_t w = 0;
+      int mb = 0;
       for (int64_t s = sl * kSlice; s < std::min(n, (sl + 1) * kSlice); ++s)
-        for (int a = 0; a < desc->m; ++a) w = std::max(w, rp[s * desc->m + a + 1] - rp[s * desc->m + a]);
-      tot += (int64_t)desc->m * w * kSlice;
+        for (int a = 0; a < m; ++a)
+          if (!adm || adm[s * m + a]) {
+            w = std::max(w, rp[s * m + a + 1] - rp[s * m + a]);
+            mb = std::max(mb, a + 1);
+          }
+      tot += (int64_t)mb * w * kSlice;
       totp += w * kSlice;
     }
-    b += round256(tot * 4) + round256(tot * vb) + 2 * round256(ns * 8) + round256(ns * 4) +
+    b += round256(tot * 4) + round256(tot * vb) + 2 * round256(ns * 8) + 2 * round256(ns * 4) +
          round256(totp * 4) + round256(totp * vb);
   } else {
     b += round256((size_t)R * n * vb);
   }
+  if (desc->admissible) b += round256(R);
   b += round256(R * 8) + round256(n * 8) + round256(sizeof(DevStatus)) +
        round256(sizeof(GivensState)) + round256(part_doubles(n) * 8) + round256(sizeof(PCtl));
   const size_t xb = fp32 ? 4 : 8;

@@ -250,7 +250,7 @@ ig_status run_eval(Mdp& d, const int32_t* pi, double* V, const ig_params& p, ig_
   if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
   k_gather(d, pi, s);
   if (ig_status e = sync_status(d, s)) return e;
-  if (d.hst->changes) return fail(IG_E_INVALID, "policy entry out of range");
+  if (d.hst->changes) return fail(IG_E_INVALID, "policy entry out of range or outside A(s)");
   k_residual(d, pi, V, d.ws.r, s);
   st.alg_bytes += Bytes{d}.residual();
   if (ig_status e = sync_status(d, s)) return e;

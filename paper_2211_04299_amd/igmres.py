@@ -44,7 +44,8 @@ class MdpDesc(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("gamma", C.c_double), ("fmt", C.c_int),
                 ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
                 ("val_type", C.c_int), ("cost", C.c_void_p), ("store", C.c_int),
-                ("inputs_on_device", C.c_int32), ("validate", C.c_int32)]
+                ("inputs_on_device", C.c_int32), ("validate", C.c_int32),
+                ("admissible", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -259,6 +260,13 @@ def _desc(mdp, store, validate):
     d.store = DTYPES[store]
     d.inputs_on_device = 0
     d.validate = int(validate)
+    adm = getattr(mdp, "adm", None)
+    if adm is not None:  # action sets A(s): admissible[s*m + a]
+        a8 = np.ascontiguousarray(np.asarray(adm).reshape(-1), dtype=np.uint8)
+        if a8.size != mdp.n * mdp.m:
+            raise ValueError("adm must hold n*m entries")
+        keep.append(a8)
+        d.admissible = a8.ctypes.data
     return d, keep
 
 

@@ -93,3 +93,37 @@ def test_server_config_default():
     c = igm().server_config_default()
     assert (c.slots, c.prep_threads, c.block_slices, c.max_states) == (4, 2, 16, 1 << 19)
     assert c.hbm_budget == 32 << 30
+
+
+# ---- action sets A(s) ------------------------------------------------------
+
+def _with_mask(mdp, adm):
+    return synth.MDP(mdp.n, mdp.m, mdp.gamma, mdp.cost, mdp.fmt, mdp.row_ptr, mdp.col, mdp.val,
+                     mdp.P, "masked", dict(mdp.meta), np.asarray(adm, bool).reshape(-1))
+
+
+def test_state_without_admissible_action():
+    m = base()
+    adm = np.ones((m.n, m.m), bool)
+    adm[3] = False
+    assert "admissible" in expect_invalid(_with_mask(m, adm))
+
+
+def test_admissible_row_must_be_nonempty():
+    m = synth.with_action_sets(base(), 0.6, 1)  # excluded rows dropped from the CSR
+    adm = m.adm.reshape(m.n, m.m).copy()
+    s, a = np.argwhere(~adm)[0]
+    adm[s, a] = True  # now admissible, but its row is empty
+    assert "non-empty" in expect_invalid(_with_mask(m, adm))
+
+
+def test_excluded_rows_and_costs_are_ignored():
+    """Empty rows and NaN costs of excluded pairs pass validation (the call
+    then fails only for want of a device here)."""
+    I = igm()
+    m = synth.with_action_sets(base(), 0.5, 2, empty_rows=True, nan_costs=True)
+    assert np.isnan(m.cost).any() and (np.diff(m.row_ptr) == 0).any()
+    try:
+        I.mdp_create(m).close()
+    except I.IgError as e:
+        assert e.status != I.IG_E_INVALID, str(e)
