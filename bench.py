@@ -227,7 +227,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the design of the sharded solve is described in DESIGN.md)", file=sys.stderr)
+              "(a solve would shard by contiguous state blocks with all-gathers and all-reduces)", file=sys.stderr)
         sys.exit(2)
 
     import torch
