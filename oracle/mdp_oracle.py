@@ -35,6 +35,13 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
                            (eq. 13) computed from an explicitly formed Krylov
                            matrix, by agreement with LU at alpha -> 0, and by
                            agreement of the returned V with PI-LU's V*.
+  neumann_apply            M^{-1} = sum_{k<=d} (gamma P^pi)^k, the truncated
+                           series of Lemma 3's proof, as a right
+                           preconditioner of the inner GMRES (future work
+                           named in Sec. 5).  Pinned by the closed form
+                           J M^{-1} = I - (gamma P^pi)^{d+1}, by the minimum-
+                           residual property over x0 + M^{-1} K_i(J M^{-1}, r0)
+                           and by degree 0 = plain GMRES.
   opi                      optimistic PI with a fixed number of VI sweeps
                            (Sec. 2.1); OPI(1) is VI.
   certificate              ||V - V*||_inf <= ||TV - V||_inf / (1 - gamma),
@@ -76,7 +83,7 @@ __all__ = [
     "q_values", "bellman", "greedy_keep", "policy_cost", "policy_matrix_dense",
     "policy_matrix_sparse", "j_apply", "policy_eval_lu", "policy_eval_neumann",
     "policy_iteration", "value_iteration", "brute_force", "gmres_inner",
-    "igmres_pi", "opi", "certificate", "action_gaps", "OracleStats",
+    "igmres_pi", "opi", "certificate", "action_gaps", "OracleStats", "neumann_apply",
 ]
 
 
@@ -161,6 +168,19 @@ def j_apply(mdp, pi, x, Ppi=None):
     if Ppi is None:
         Ppi = policy_matrix_sparse(mdp, pi)
     return x - mdp.gamma * (Ppi @ x)
+
+
+def neumann_apply(mdp, pi, x, degree, Ppi=None):
+    """M^{-1} x = sum_{k=0}^{degree} (gamma P^pi)^k x, the truncated Neumann
+    series of J^{-1} = (I - gamma P^pi)^{-1} (the series of Lemma 3's proof),
+    by Horner's rule y <- x + gamma P^pi y.  degree 0 is the identity."""
+    if Ppi is None:
+        Ppi = policy_matrix_sparse(mdp, pi)
+    x = np.asarray(x, np.float64)
+    y = x.copy()
+    for _ in range(degree):
+        y = x + mdp.gamma * (Ppi @ y)
+    return y
 
 
 def policy_eval_lu(mdp, pi):
@@ -266,7 +286,7 @@ def _lsq(H, i, beta):
     return y
 
 
-def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=False):
+def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=False, precond=0):
     """The inner while-loop of Algorithm 2 for J = I - gamma P^pi, b = g^pi.
 
     Starting at x0, runs restarted GMRES(W) (Arnoldi with modified
@@ -279,6 +299,11 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
     (the quantity GMRES minimises) by less than a factor 1 - 1e-6: restarted
     GMRES(W) with W < n can stagnate completely, and rounding puts a floor
     under the residual.
+    precond = d > 0 runs right-preconditioned GMRES with M^{-1} the degree-d
+    Neumann polynomial (neumann_apply): Arnoldi on J M^{-1}, iterates
+    x = x_cycle + M^{-1} Q y.  The residual it minimises and the stopping
+    test stay those of J itself (the preconditioner the paper names as
+    future work, Sec. 5; this polynomial is one choice).
     Returns (x, info) with info = dict(steps, restarts, breakdown, H_first,
     iterates (if trace), res_inf).
     """
@@ -286,6 +311,7 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
     Ppi = policy_matrix_sparse(mdp, pi)
     b = policy_cost(mdp, pi)
     J = lambda v: j_apply(mdp, pi, v, Ppi)  # noqa: E731
+    Minv = lambda v: neumann_apply(mdp, pi, v, precond, Ppi)  # noqa: E731
 
     x_cycle = np.asarray(x0, np.float64).copy()   # iterate at the cycle start
     x = x_cycle.copy()
@@ -306,7 +332,7 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
     res_inf = float(np.max(np.abs(r)))
     stagnated = False
     while res_inf > thr and steps < max_inner:
-        q = J(Q[:, i])
+        q = J(Minv(Q[:, i]))
         for j in range(i + 1):                    # modified Gram-Schmidt
             H[j, i] = Q[:, j] @ q
             q = q - H[j, i] * Q[:, j]
@@ -314,7 +340,7 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
         steps += 1
         if H[i + 1, i] == 0.0:                    # lucky breakdown
             y = _lsq(H, i + 1, beta)
-            x = x_cycle + Q[:, :i + 1] @ y
+            x = x_cycle + Minv(Q[:, :i + 1] @ y)
             breakdown = True
             res_inf = float(np.max(np.abs(b - J(x))))
             if trace:
@@ -322,7 +348,7 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
             break
         Q[:, i + 1] = q / H[i + 1, i]
         y = _lsq(H, i + 1, beta)
-        x = x_cycle + Q[:, :i + 1] @ y
+        x = x_cycle + Minv(Q[:, :i + 1] @ y)
         if trace and restarts == 0:
             iterates.append(x.copy())
         r = b - J(x)
@@ -350,7 +376,8 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
                    iterates=iterates, res_inf=res_inf, thr=thr, stagnated=stagnated)
 
 
-def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inner=10_000):
+def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inner=10_000,
+              precond=0):
     """Algorithm 2 with outer termination at ||T V_k - V_k||_inf <= tol.
 
     alpha defaults to the midpoint of Theorem 1's admissible range,
@@ -371,7 +398,7 @@ def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inne
             return V, pi, st
         Phi = policy_cost(mdp, pi) - j_apply(mdp, pi, V)
         V, info = gmres_inner(mdp, pi, V, alpha, W, max_inner,
-                              ref_inf=float(np.max(np.abs(Phi))))
+                              ref_inf=float(np.max(np.abs(Phi))), precond=precond)
         st.inner += info["steps"]
         st.restarts += info["restarts"]
         st.breakdowns += int(info["breakdown"])

@@ -367,3 +367,67 @@ def test_action_sets_igmres_pi_reaches_masked_optimum():
     gaps = O.action_gaps(mdp, Vs)
     sel = gaps > 1e-9
     assert np.array_equal(pi[sel], pis[sel])
+
+
+# ---- right preconditioning with the truncated Neumann series ----------------
+
+@pytest.mark.parametrize("d", [1, 2, 5])
+def test_neumann_closed_form(d):
+    """J M^{-1} = I - (gamma P^pi)^{d+1} for M^{-1} = sum_{k<=d} (gamma P^pi)^k
+    (the two commute); the right side is formed by repeated products."""
+    mdp = synth.sparse_uniform(60, 3, 6, 0.97, seed=21)
+    pi = np.random.default_rng(2).integers(0, 3, size=60).astype(np.int32)
+    x = np.random.default_rng(3).normal(size=60)
+    lhs = O.j_apply(mdp, pi, O.neumann_apply(mdp, pi, x, d))
+    Ppi = O.policy_matrix_dense(mdp, pi)
+    p = x.copy()
+    for _ in range(d + 1):
+        p = mdp.gamma * (Ppi @ p)
+    np.testing.assert_allclose(lhs, x - p, rtol=1e-12, atol=1e-12)
+    # and M^{-1} -> J^{-1} as d grows (Lemma 3's series)
+    big = O.neumann_apply(mdp, pi, x, 3000)
+    np.testing.assert_allclose(O.j_apply(mdp, pi, big), x, rtol=1e-9, atol=1e-9)
+
+
+def test_preconditioned_gmres_minimum_residual_property():
+    """Right-preconditioned GMRES: x_i = argmin ||b - J x||_2 over
+    x0 + M^{-1} K_i(J M^{-1}, r0), from an explicitly formed Krylov matrix."""
+    d = 2
+    mdp = synth.sparse_uniform(40, 3, 5, 0.95, seed=7)
+    pi = np.random.default_rng(3).integers(0, 3, size=40).astype(np.int32)
+    x0 = np.random.default_rng(4).normal(size=40)
+    _, info = O.gmres_inner(mdp, pi, x0, alpha=1e-15, W=8, trace=True, max_inner=6, precond=d)
+    b = O.policy_cost(mdp, pi)
+    J = lambda v: O.j_apply(mdp, pi, v)  # noqa: E731
+    Minv = lambda v: O.neumann_apply(mdp, pi, v, d)  # noqa: E731
+    r0 = b - J(x0)
+    K = [r0 / np.linalg.norm(r0)]
+    for xi in info["iterates"]:
+        MK = np.stack([Minv(v) for v in K], axis=1)
+        JMK = np.stack([J(v) for v in MK.T], axis=1)
+        c, *_ = np.linalg.lstsq(JMK, r0, rcond=None)
+        np.testing.assert_allclose(xi, x0 + MK @ c, rtol=1e-9, atol=1e-9)
+        nxt = J(Minv(K[-1]))
+        K.append(nxt / np.linalg.norm(nxt))
+
+
+def test_preconditioner_degree_zero_is_plain_gmres():
+    mdp = synth.config("c1", 0)
+    V1, pi1, st1 = O.igmres_pi(mdp, W=20, tol=1e-10)
+    V2, pi2, st2 = O.igmres_pi(mdp, W=20, tol=1e-10, precond=0)
+    assert np.array_equal(V1, V2) and np.array_equal(pi1, pi2) and st1.inner == st2.inner
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_preconditioned_igmres_reaches_optimum_in_fewer_steps(d):
+    mdp = synth.config("c1", 1)
+    Vs, pis, _ = O.policy_iteration(mdp)
+    tol = 1e-11 * np.max(np.abs(Vs))
+    V0, _, st0 = O.igmres_pi(mdp, W=20, tol=tol)
+    V, pi, st = O.igmres_pi(mdp, W=20, tol=tol, precond=d)
+    assert st.converged
+    assert np.max(np.abs(V - Vs)) <= 1e-9 * np.max(np.abs(Vs))
+    sel = O.action_gaps(mdp, Vs) > 1e-9
+    assert np.array_equal(pi[sel], pis[sel])
+    # each preconditioned step covers d+1 products: fewer Arnoldi steps
+    assert st.inner < st0.inner
