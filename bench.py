@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--prep-threads", type=int, default=4)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--precond", type=int, default=0,
+                    help="degree of the Neumann right preconditioner of the inner GMRES (stream engine)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -260,7 +262,8 @@ def main():
     info = h.info()
     V = torch.zeros(mdp.n, dtype=torch.float64, device=dev)
     pi = torch.zeros(mdp.n, dtype=torch.int32, device=dev)
-    params = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8, mode=wl["mode"])
+    params = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8, mode=wl["mode"],
+                                   precond=args.precond)
 
     def step():
         V.zero_()
@@ -328,8 +331,9 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}", "seed": args.seed,
                    "n": mdp.n, "m": mdp.m, "nnz": int(info.nnz), "restart": restart,
                    "engine": ("persistent (one cooperative launch per solve, "
-                              f"{info.persistent_blocks} blocks)") if info.persistent_ok
-                   else "stream (one launch per step)"},
+                              f"{info.persistent_blocks} blocks)") if info.persistent_ok and not args.precond
+                   else "stream (one launch per step)",
+                   "precond_degree": args.precond},
         "time_to_tol_ms": round(ms_step, 4),
         "solve": {"outer": st["outer"], "inner": st["inner"], "restarts": st["restarts"],
                   "explicit_residuals": st["explicit_residuals"], "res_inf": st["res_inf"],

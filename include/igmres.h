@@ -124,6 +124,12 @@ typedef struct {
                           from the shape); clamped so that a workgroup owns
                           1..32 slices.  The result depends on this count
                           (reduction order), never on other device work.      */
+  int32_t precond;     /* inner GMRES right-preconditioned by the truncated
+                          Neumann series M^{-1} = sum_{k<=precond} (gamma
+                          P^pi)^k (the preconditioner Section 5 leaves to
+                          future work); 0..16, 0 = none.  Stopping tests stay
+                          on the true residual of J.  Stream engine only:
+                          engine 0 then takes it, engine 2 is rejected.       */
 } ig_params;
 
 typedef struct {
@@ -153,7 +159,7 @@ typedef struct ig_mdp_s* ig_mdp_t;
 /* Fill `p` with defaults for discount gamma: alpha = (1-gamma)/(2(1+gamma))
  * (midpoint of Theorem 1's range), restart 30, max_outer 1000,
  * max_inner 100000, tol 1e-8, FP64 mode, opi_sweeps 20, forcing 0,
- * eval_rtol 1e-13, engine 0, blocks 0. */
+ * eval_rtol 1e-13, engine 0, blocks 0, precond 0. */
 void ig_params_default(ig_params* p, double gamma);
 
 /* Copy P and g to the device in the GPU layout (sliced ELL, 64 states per

@@ -29,6 +29,8 @@ enum KClass { KC_BELLMAN = 0, KC_JAPPLY, KC_GS, KC_UPDATE, KC_RESID, KC_VI, KC_O
 struct Workspace {
   int W = 0;           // restart capacity
   bool fp32 = false;   // basis type
+  double* pa = nullptr;  // preconditioner ping-pong vectors (n doubles each;
+  double* pb = nullptr;  // hold FP32 values in mixed mode)
   void* Q = nullptr;   // (W+1) x n basis, column j at Q + j*n
   void* wA = nullptr;  // Arnoldi vectors (ping-pong)
   void* wB = nullptr;
@@ -192,6 +194,14 @@ void launch_dots(Mdp& d, bool fp32, int cnt, const void* v, bool givens, bool wi
 // w1 = y - sum_{j<cnt} gs->h_j Q_j
 // one Arnoldi step's orthogonalisation (after the J-apply): fused two-pass
 // form for columns up to gs_fused_max, else the four-kernel sequence
+// Horner step of the Neumann preconditioner: y = x*sx + gamma*(P^pi z)*sz,
+// sx/sz = 1 / *ptr (null: 1)
+void launch_pstep_sparse(Mdp& d, bool fp32, const void* x, const double* sx, const void* z,
+                         const double* sz, void* y, hipStream_t s);
+void launch_pstep_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* sx,
+                        const void* z, const double* sz, void* y, hipStream_t s);
+void launch_vadd(Mdp& d, const double* a, const double* b, double* out, hipStream_t s);
+ig_status ensure_precond(Mdp& d);
 void launch_gs_step(Mdp& d, bool fp32, int c, const void* y, void* w1, hipStream_t s);
 int gs_fused_max(bool fp32);
 void launch_axpy(Mdp& d, bool fp32, int cnt, const void* y, void* w1, hipStream_t s);

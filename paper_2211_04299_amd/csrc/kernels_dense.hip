@@ -181,6 +181,26 @@ __global__ __launch_bounds__(kBlock) void k_japply_dense(const VT* __restrict__ 
   }
 }
 
+// Horner step of the Neumann preconditioner: y = x * sx + gamma * (P^pi z) * sz
+template <typename VT, typename XT, typename AT>
+__global__ __launch_bounds__(kBlock) void k_pstep_dense(const VT* __restrict__ P, int m,
+                                                        int64_t n, AT gamma,
+                                                        const int32_t* __restrict__ pi,
+                                                        const XT* __restrict__ x,
+                                                        const double* __restrict__ sx,
+                                                        const XT* __restrict__ z,
+                                                        const double* __restrict__ sz,
+                                                        XT* __restrict__ y, bool vec_ok) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const AT ax = sx ? (AT)(1.0 / *sx) : (AT)1, az = sz ? (AT)(1.0 / *sz) : (AT)1;
+  for (int64_t s = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; s < n;
+       s += (int64_t)gridDim.x * kWpb) {
+    const AT acc = dense_row_dot<VT, XT, AT>(P + ((int64_t)s * m + pi[s]) * n, n, z, (XT)1, lane,
+                                             vec_ok);
+    if (lane == 0) y[s] = (XT)((AT)x[s] * ax + gamma * acc * az);
+  }
+}
+
 // MODE 0: residual r = g^pi - (V - gamma P^pi V); MODE 1: VI sweep
 // Vout = g^pi + gamma P^pi Vin.  Partials {max|.|, ||.||^2, max|V| (MODE 0)}.
 template <typename VT, int MODE>
@@ -284,6 +304,22 @@ void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, co
       hipLaunchKernelGGL((k_japply_dense<VT, double, double>), dim3(grid_waves(d.n)),
                          dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma, pi,
                          (const double*)x, eta, (double*)y, vec_ok(d));
+  });
+}
+
+void launch_pstep_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* sx,
+                        const void* z, const double* sz, void* y, hipStream_t s) {
+  ProfScope p(d, KC_JAPPLY, s);
+  by_store(d, [&](auto t) {
+    using VT = decltype(t);
+    if (fp32)
+      hipLaunchKernelGGL((k_pstep_dense<VT, float, float>), dim3(grid_waves(d.n)), dim3(kBlock), 0,
+                         s, (const VT*)d.P, d.m, d.n, (float)d.gamma, pi, (const float*)x, sx,
+                         (const float*)z, sz, (float*)y, vec_ok(d));
+    else
+      hipLaunchKernelGGL((k_pstep_dense<VT, double, double>), dim3(grid_waves(d.n)), dim3(kBlock),
+                         0, s, (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)x, sx,
+                         (const double*)z, sz, (double*)y, vec_ok(d));
   });
 }
 

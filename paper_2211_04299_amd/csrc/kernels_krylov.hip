@@ -331,8 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_form_q0(const double* __restrict__ r
   }
 }
 
-// V = Vb + sum_{j<i} y_j Q_j, y from R y = g_hat (each block solves the
-// i x i triangular system itself)
+// V = Vb + sum_{j<i} y_j Q_j (Vb null: the sum alone), y from R y = g_hat
+// (each block solves the i x i triangular system itself)
 template <typename XT>
 __global__ __launch_bounds__(kBlock) void k_update(const XT* __restrict__ Q, int64_t n, int i,
                                                    const GivensState* __restrict__ gs,
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const XT* __restrict__ Q, int
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += stride) {
-    double v0 = Vb[s], v1 = 0.0;
+    double v0 = Vb ? Vb[s] : 0.0, v1 = 0.0;
     int j = 0;
     for (; j + 2 <= i; j += 2) {
       v0 = fma(y[j], to_d(qcol(Q, n, j)[s]), v0);
@@ -359,6 +359,15 @@ __global__ __launch_bounds__(kBlock) void k_update(const XT* __restrict__ Q, int
     if (j < i) v0 = fma(y[j], to_d(qcol(Q, n, j)[s]), v0);
     V[s] = v0 + v1;
   }
+}
+
+// out = a + b (FP64 vectors)
+__global__ __launch_bounds__(kBlock) void k_vadd(const double* __restrict__ a,
+                                                 const double* __restrict__ b, int64_t n,
+                                                 double* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += stride)
+    out[s] = a[s] + b[s];
 }
 
 // One-block finishing kernel: reduce cnt columns of per-block partials
@@ -617,6 +626,11 @@ void launch_axpy(Mdp& d, bool fp32, int cnt, const void* y, void* w1, hipStream_
     hipLaunchKernelGGL(k_axpy<double>, dim3(gs_grid(d)), dim3(kBlock), 0, s,
                        (const double*)d.ws.Q, d.n, cnt, (const GivensState*)d.gs, (const double*)y,
                        (double*)w1);
+}
+
+void launch_vadd(Mdp& d, const double* a, const double* b, double* out, hipStream_t s) {
+  ProfScope p(d, KC_UPDATE, s);
+  hipLaunchKernelGGL(k_vadd, dim3(gs_grid(d)), dim3(kBlock), 0, s, a, b, d.n, out);
 }
 
 void launch_update(Mdp& d, bool fp32, int i, const double* Vb, double* V, hipStream_t s) {

@@ -173,6 +173,32 @@ __global__ __launch_bounds__(kBlock) void k_japply(SellPi<VT> Pp, int64_t n, AT 
   }
 }
 
+// One Horner step of the Neumann preconditioner M^{-1} = sum_{k<=d} (gamma
+// P^pi)^k:  y = x * sx + gamma * (P^pi z) * sz  (sx, sz = 1 / *eta or 1).
+template <typename VT, typename XT, typename AT, int G>
+__global__ __launch_bounds__(kBlock) void k_pstep(SellPi<VT> Pp, int64_t n, AT gamma,
+                                                  const XT* __restrict__ x,
+                                                  const double* __restrict__ sx,
+                                                  const XT* __restrict__ z,
+                                                  const double* __restrict__ sz,
+                                                  XT* __restrict__ y) {
+  constexpr int S = kWave / G;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ls = lane % S, g = lane / S;
+  const int64_t nw = (n + S - 1) / S;
+  const int64_t wstride = (int64_t)gridDim.x * (kBlock / kWave);
+  const AT ax = sx ? (AT)(1.0 / *sx) : (AT)1, az = sz ? (AT)(1.0 / *sz) : (AT)1;
+  for (int64_t w = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; w < nw;
+       w += wstride) {
+    const int64_t s = w * S + ls;
+    const int64_t b = s >> 6;
+    const int l = (int)(s & 63);
+    const AT acc = group_sum<AT, G>(
+        ell_row<VT, XT, AT, G>(Pp.col, Pp.val, Pp.off[b] + l, Pp.width[b], g, z, (XT)1));
+    if (s < n && g == 0) y[s] = (XT)((AT)x[s] * ax + gamma * acc * az);
+  }
+}
+
 // MODE 0: r = g^pi - (V - gamma P^pi V), partials {max|r|, ||r||^2, max|V|}
 // MODE 1: Vout = g^pi + gamma P^pi Vin, partials {max|Vout - Vin|, ||.||^2, 0}
 template <typename VT, int G, int MODE>
@@ -312,6 +338,21 @@ struct RunJapply {
 };
 
 template <typename VT, int G>
+struct RunPstep {
+  static void run(Mdp& d, bool fp32, const void* x, const double* sx, const void* z,
+                  const double* sz, void* y, hipStream_t s) {
+    if (fp32)
+      hipLaunchKernelGGL((k_pstep<VT, float, float, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
+                         viewPi<VT>(d), d.n, (float)d.gamma, (const float*)x, sx, (const float*)z,
+                         sz, (float*)y);
+    else
+      hipLaunchKernelGGL((k_pstep<VT, double, double, G>), dim3(grid_for(d, G)), dim3(kBlock), 0,
+                         s, viewPi<VT>(d), d.n, d.gamma, (const double*)x, sx, (const double*)z,
+                         sz, (double*)y);
+  }
+};
+
+template <typename VT, int G>
 struct RunResidual {
   static void run(Mdp& d, const double* V, double* r, hipStream_t s) {
     hipLaunchKernelGGL((k_policy_pass<VT, G, 0>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
@@ -351,6 +392,12 @@ void launch_japply_sparse(Mdp& d, bool fp32, const void* x, const double* eta, v
                           hipStream_t s) {
   ProfScope p(d, KC_JAPPLY, s);
   dispatch_vt_g<RunJapply>(d, d.G_jap, d, fp32, x, eta, y, s);
+}
+
+void launch_pstep_sparse(Mdp& d, bool fp32, const void* x, const double* sx, const void* z,
+                         const double* sz, void* y, hipStream_t s) {
+  ProfScope p(d, KC_JAPPLY, s);
+  dispatch_vt_g<RunPstep>(d, d.G_jap, d, fp32, x, sx, z, sz, y, s);
 }
 
 void launch_residual_sparse(Mdp& d, const double* V, double* r, hipStream_t s) {

@@ -264,6 +264,7 @@ void free_all(Mdp* d) {
   F(d->adm);
   F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->pctl);
   F(d->ws.Q); F(d->ws.wA); F(d->ws.wB); F(d->ws.Vb); F(d->ws.r); F(d->ws.t); F(d->ws.pi);
+  F(d->ws.pa); F(d->ws.pb);
   if (d->own_host_mirrors) {
     if (d->hst) (void)hipHostFree(d->hst);
     if (d->hpctl) (void)hipHostFree(d->hpctl);
@@ -645,6 +646,15 @@ void PinnedStage::release() {
   cap = 0;
 }
 
+// the two n-vectors of the Neumann preconditioner (stream engine only)
+ig_status ensure_precond(Mdp& d) {
+  if (d.ws.pa) return IG_OK;
+  if (d.region) return fail(IG_E_INVALID, "a region handle has no preconditioner buffers");
+  if (dmalloc(&d.ws.pa, (size_t)d.n * 8) || dmalloc(&d.ws.pb, (size_t)d.n * 8))
+    return fail(IG_E_NOMEM, "preconditioner buffers");
+  return IG_OK;
+}
+
 // create_impl with the handle's region (if any) as the allocation target
 ig_status create_in(const ig_mdp_desc* desc, Mdp* d) {
   struct RegionScope {
@@ -741,6 +751,7 @@ void ig_params_default(ig_params* p, double gamma) {
   p->eval_rtol = 1e-13;
   p->engine = 0;
   p->blocks = 0;
+  p->precond = 0;
 }
 
 ig_status mdp_create(const ig_mdp_desc* desc, void* stream, ig_mdp_t* out) {

@@ -497,6 +497,7 @@ ig_status srv_submit(ig_server_t srv, const ig_mdp_desc* desc, const double* V0,
   if (!(p.tol > 0.0)) return fail(IG_E_INVALID, "tol must be > 0");
   if (p.mode != IG_MODE_FP64 && p.mode != IG_MODE_MIXED) return fail(IG_E_INVALID, "bad mode");
   if (p.blocks < 0) return fail(IG_E_INVALID, "blocks must be >= 0");
+  if (p.precond != 0) return fail(IG_E_INVALID, "serving runs the persistent engine: precond must be 0");
   auto r = std::make_unique<Req>();
   r->desc = *desc;
   r->p = p;

@@ -5,6 +5,7 @@
 // the few scalars that decide the control flow.
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "internal.hpp"
 
@@ -30,6 +31,13 @@ void k_japply(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double*
     launch_japply_sparse(d, fp32, x, eta, y, s);
   else
     launch_japply_dense(d, fp32, pi, x, eta, y, s);
+}
+void k_pstep(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* sx, const void* z,
+             const double* sz, void* y, hipStream_t s) {
+  if (d.fmt == IG_FMT_CSR)
+    launch_pstep_sparse(d, fp32, x, sx, z, sz, y, s);
+  else
+    launch_pstep_dense(d, fp32, pi, x, sx, z, sz, y, s);
 }
 void k_residual(Mdp& d, const int32_t* pi, const double* V, double* r, hipStream_t s) {
   if (d.fmt == IG_FMT_CSR)
@@ -87,11 +95,30 @@ struct Inner {
 // vector), then two Gram-Schmidt passes and the Givens update; the residual
 // of column c-1's iterate, ||Q z||_inf, arrives with the step of column c.
 // A stop is always confirmed on the true FP64 residual g - J V.
+//
+// precond = d > 0: right preconditioning with the truncated Neumann series
+// M^{-1} = sum_{k<=d} (gamma P^pi)^k (Horner steps).  Arnoldi runs on
+// J M^{-1} and iterates are V = Vb + M^{-1} Q y; the residual and every test
+// stay those of J, so the implicit residual Q z is still g - J V.
 ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double r_l2sq,
                       const double* r_l2sq_dev, double thr, int W, int max_inner, bool fp32,
-                      hipStream_t s, Inner& out) {
+                      int precond, hipStream_t s, Inner& out) {
   Workspace& ws = d.ws;
   const Bytes B{d};
+  if (precond > 0)
+    if (ig_status e = ensure_precond(d)) return e;
+  // M^{-1}(src * sc) by `precond` Horner steps into ws.pa / ws.pb
+  auto minv = [&](bool f32, const void* src, const double* sc) -> const void* {
+    void* a = ws.pa;
+    void* b = ws.pb;
+    k_pstep(d, f32, pi, src, sc, src, sc, a, s);
+    for (int k = 1; k < precond; ++k) {
+      k_pstep(d, f32, pi, src, sc, a, nullptr, b, s);
+      std::swap(a, b);
+    }
+    out.bytes += precond * B.japply(f32);
+    return a;
+  };
   out.res_inf = r_inf;
   if (r_inf <= thr) {
     out.met = true;
@@ -108,7 +135,12 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
 
   // V = Vb + Q_{0..cnt-1} y and its true residual (FP64)
   auto explicit_residual = [&](int cnt) -> ig_status {
-    launch_update(d, fp32, cnt, ws.Vb, V, s);
+    if (precond == 0) {
+      launch_update(d, fp32, cnt, ws.Vb, V, s);
+    } else {  // V = Vb + M^{-1} (Q y), the products in FP64
+      launch_update(d, fp32, cnt, nullptr, V, s);
+      launch_vadd(d, ws.Vb, (const double*)minv(false, V, nullptr), V, s);
+    }
     k_residual(d, pi, V, ws.r, s);
     out.bytes += B.update(fp32, cnt) + B.residual();
     ++out.expl;
@@ -118,7 +150,9 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
   };
 
   for (int c = 0;;) {
-    if (c == 0)
+    if (precond > 0)
+      k_japply(d, fp32, pi, minv(fp32, c == 0 ? ws.Q : w1, c == 0 ? nullptr : eta_dev), nullptr, y, s);
+    else if (c == 0)
       k_japply(d, fp32, pi, ws.Q, nullptr, y, s);
     else
       k_japply(d, fp32, pi, w1, eta_dev, y, s);
@@ -180,6 +214,9 @@ ig_status check_params(const Mdp& d, const ig_params* p, bool need_alpha) {
   if (!(p->tol > 0.0)) return fail(IG_E_INVALID, "tol must be > 0");
   if (p->mode != IG_MODE_FP64 && p->mode != IG_MODE_MIXED) return fail(IG_E_INVALID, "bad mode");
   if (p->blocks < 0) return fail(IG_E_INVALID, "blocks must be >= 0");
+  if (p->precond < 0 || p->precond > 16) return fail(IG_E_INVALID, "precond must be in 0..16");
+  if (p->precond > 0 && p->engine == 2)
+    return fail(IG_E_INVALID, "the persistent engine has no preconditioner (use engine 0 or 1)");
   (void)d;
   return IG_OK;
 }
@@ -221,7 +258,7 @@ ig_status run_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stat
                      hipStream_t s) {
   const bool fp32 = p.mode == IG_MODE_MIXED;
   if (p.engine < 0 || p.engine > 2) return fail(IG_E_INVALID, "engine must be 0, 1 or 2");
-  if (p.engine == 2 || (p.engine == 0 && d.coop && persistent_fits(d)))
+  if (p.engine == 2 || (p.engine == 0 && p.precond == 0 && d.coop && persistent_fits(d)))
     return persistent_igmres(d, V, pi, p, st, s);
   if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
   for (int k = 0;; ++k) {
@@ -238,7 +275,7 @@ ig_status run_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stat
     const double alpha = p.forcing ? std::min(p.alpha, std::sqrt(res)) : p.alpha;
     Inner in;
     if (ig_status e = gmres_inner(d, pi, V, res, d.hst->phi_l2sq, &d.st->phi_l2sq, alpha * res,
-                                  p.restart, p.max_inner, fp32, s, in))
+                                  p.restart, p.max_inner, fp32, p.precond, s, in))
       return e;
     add_inner(st, in);
   }
@@ -257,7 +294,8 @@ ig_status run_eval(Mdp& d, const int32_t* pi, double* V, const ig_params& p, ig_
   if (!std::isfinite(d.hst->res_inf)) return fail(IG_E_NUMERIC, "non-finite residual");
   Inner in;
   if (ig_status e = gmres_inner(d, pi, V, d.hst->res_inf, d.hst->res_l2sq, &d.st->res_l2sq,
-                                p.alpha * d.hst->res_inf, p.restart, p.max_inner, fp32, s, in))
+                                p.alpha * d.hst->res_inf, p.restart, p.max_inner, fp32, p.precond, s,
+                                in))
     return e;
   add_inner(st, in);
   st.res_inf = in.res_inf;
@@ -280,7 +318,7 @@ ig_status run_pi(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& s
     if (ig_status e = sync_status(d, s)) return e;
     Inner in;
     if (ig_status e = gmres_inner(d, pi, V, d.hst->res_inf, d.hst->res_l2sq, &d.st->res_l2sq, thr,
-                                  p.restart, p.max_inner, fp32, s, in))
+                                  p.restart, p.max_inner, fp32, p.precond, s, in))
       return e;
     add_inner(st, in);
     // improvement, keeping the incumbent unless strictly better by the tie margin

@@ -1,0 +1,98 @@
+"""Right-preconditioned inner GMRES (truncated Neumann series of degree d)
+on the GPU against the FP64 oracle, which runs the same preconditioned
+Algorithm 2 (pinned by the closed form J M^{-1} = I - (gamma P^pi)^{d+1} and
+the preconditioned minimum-residual property)."""
+import numpy as np
+import pytest
+
+from oracle import mdp_oracle as O
+from paper_2211_04299_amd import synth
+
+from gpu_helpers import assert_policy_match, dev_vec, host, rel_err, tol_par, zeros
+
+pytestmark = pytest.mark.gpu
+
+
+def igm():
+    from paper_2211_04299_amd import igmres
+    return igmres
+
+
+_cache = {}
+
+
+def reference(name):
+    if name not in _cache:
+        if name == "dense":
+            mdp = synth.dense_exp(300, 4, 0.95, 3)
+        elif name == "mid":
+            mdp = synth.sparse_band(20000, 6, 10, 0.99, 5)
+        else:
+            mdp = synth.config(name, 0)
+        Vs, pis, _ = O.policy_iteration(mdp) if mdp.n <= 10000 else (None, None, None)
+        _cache[name] = (mdp, Vs, pis)
+    return _cache[name]
+
+
+def solve(mdp, store="fp64", **kw):
+    I = igm()
+    with I.mdp_create(mdp, store=store) as h:
+        V = zeros(mdp.n)
+        pi = zeros(mdp.n, "int32")
+        st = h.igmres_pi_solve(V, pi, I.params_default(mdp.gamma, **kw))
+        return host(V), host(pi), st
+
+
+@pytest.mark.parametrize("d", [1, 2, 4])
+def test_precond_c1_parity_and_steps(d):
+    mdp, Vs, pis = reference("c1")
+    tol = tol_par(mdp, np.max(np.abs(Vs)))
+    V, pi, st = solve(mdp, tol=tol, restart=20, precond=d)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+    _, _, sto = O.igmres_pi(mdp, W=20, tol=tol, precond=d)
+    assert st["outer"] == sto.outer
+    assert abs(st["inner"] - sto.inner) <= sto.outer
+
+
+@pytest.mark.parametrize("name,d", [("c2", 1), ("c2", 3), ("dense", 2)])
+def test_precond_parity(name, d):
+    mdp, Vs, pis = reference(name)
+    tol = tol_par(mdp, np.max(np.abs(Vs)))
+    V, pi, st = solve(mdp, tol=tol, precond=d)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+    _, _, st0 = solve(mdp, tol=tol)  # fewer Arnoldi steps than unpreconditioned
+    assert st["inner"] < st0["inner"]
+
+
+def test_precond_mixed_certificate():
+    mdp, _, _ = reference("mid")
+    stored = mdp.with_values(val=synth.round_values(mdp.val, "fp32"))
+    ref = mdp.with_values(val=synth.upcast_values(stored.val, "fp32"))
+    V, pi, st = solve(stored, store="fp32", tol=1e-8, mode="mixed", precond=2)
+    TV, pio, res = O.bellman(ref, V)
+    assert st["converged"] == 1 and res <= 1e-8 * (1 + 1e-6)
+    assert res / (1 - mdp.gamma) / np.max(np.abs(TV)) <= 1e-6
+
+
+def test_precond_policy_evaluation():
+    I = igm()
+    mdp, Vs, pis = reference("c1")
+    with I.mdp_create(mdp) as h:
+        V = zeros(mdp.n)
+        h.policy_eval_gmres(dev_vec(pis.astype(np.int32), "int32"), V,
+                            I.params_default(mdp.gamma, alpha=1e-13, precond=3))
+        assert rel_err(host(V), O.policy_eval_lu(mdp, pis)) <= 1e-10
+
+
+def test_precond_rejected_by_persistent_engine():
+    I = igm()
+    mdp, _, _ = reference("c1")
+    with I.mdp_create(mdp) as h:
+        with pytest.raises(I.IgError) as e:
+            h.igmres_pi_solve(zeros(mdp.n), zeros(mdp.n, "int32"),
+                              I.params_default(mdp.gamma, engine=2, precond=1))
+        assert e.value.status == I.IG_E_INVALID
