@@ -100,6 +100,7 @@ struct Mdp {
   PCtl* pctl = nullptr;         // persistent-solve control block (device)
   PCtl* hpctl = nullptr;        // pinned host mirror
   int num_cu = 0;
+  int max_lds = 65536;          // LDS bytes a workgroup may use
   bool coop = false;            // cooperative launch supported
   Workspace ws;
 

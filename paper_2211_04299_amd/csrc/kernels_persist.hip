@@ -196,14 +196,24 @@ __device__ __forceinline__ int pow2_ceil(int x) {
   return p;
 }
 
+// The block's rows of the Krylov basis: row t of column j at base[j*ld + t]
+// (LDS-resident with ld = the padded own-row count, or the global basis with
+// base = Q + s_lo and ld = n).
+template <typename XT>
+struct QView {
+  XT* base;
+  int64_t ld;
+  __device__ __forceinline__ XT& at(int j, int t) const { return base[(int64_t)j * ld + t]; }
+};
+
 // partial dots <Q_j, wl> (own rows) for j < cnt into mypart[0..cnt); with_norm
 // adds ||wl||^2 as mypart[cnt].  Groups of gsz threads (a power of two,
 // 8..64) per j; every thread sums a strided subset of the own rows with its
 // loads issued together, then the group reduces with shuffles.
 template <typename XT>
-__device__ __forceinline__ void own_dots(const XT* __restrict__ Q, int64_t n, int cnt,
-                                         int64_t s_lo, int nown, const double* __restrict__ wl,
-                                         double* mypart, bool with_norm) {
+__device__ __forceinline__ void own_dots(QView<XT> Q, int cnt, int nown,
+                                         const double* __restrict__ wl, double* mypart,
+                                         bool with_norm) {
   const int tot = cnt + (with_norm ? 1 : 0);
   const int gsz = max(8, min(64, kPB / pow2_ceil(tot)));
   const int sub = threadIdx.x & (gsz - 1);
@@ -211,7 +221,7 @@ __device__ __forceinline__ void own_dots(const XT* __restrict__ Q, int64_t n, in
     const int j = j0 + threadIdx.x / gsz;
     double a0 = 0.0, a1 = 0.0;
     if (j < cnt) {
-      const XT* q = Q + (int64_t)j * n + s_lo;
+      const XT* q = &Q.at(j, 0);
       int t = sub;
       for (; t + gsz < nown; t += 2 * gsz) {
         a0 = fma(to_d(q[t]), wl[t], a0);
@@ -232,10 +242,9 @@ __device__ __forceinline__ void own_dots(const XT* __restrict__ Q, int64_t n, in
 // The block splits the j range over `parts` thread groups when the own rows
 // are few, and combines the partial sums in a fixed order through LDS.
 template <typename XT, typename Base, typename Out>
-__device__ __forceinline__ void own_axpy(const XT* __restrict__ Q, int64_t n, int64_t s_lo,
-                                         int nown, int cnt, const double* __restrict__ coef,
-                                         double sign, double* psum /* LDS, kPB */, Base base,
-                                         Out out) {
+__device__ __forceinline__ void own_axpy(QView<XT> Q, int nown, int cnt,
+                                         const double* __restrict__ coef, double sign,
+                                         double* psum /* LDS, kPB */, Base base, Out out) {
   const int parts = nown >= kPB ? 1 : max(1, min(8, kPB / pow2_ceil(nown)));
   const int span = kPB / parts;  // states per pass
   const int p = threadIdx.x / span, tl = threadIdx.x % span;
@@ -243,14 +252,13 @@ __device__ __forceinline__ void own_axpy(const XT* __restrict__ Q, int64_t n, in
     const int t = t0 + tl;
     double acc = 0.0;
     if (t < nown) {
-      const int64_t s = s_lo + t;
       double a0 = 0.0, a1 = 0.0;
       int j = p;
       for (; j + parts < cnt; j += 2 * parts) {
-        a0 = fma(coef[j], to_d(Q[(int64_t)j * n + s]), a0);
-        a1 = fma(coef[j + parts], to_d(Q[(int64_t)(j + parts) * n + s]), a1);
+        a0 = fma(coef[j], to_d(Q.at(j, t)), a0);
+        a1 = fma(coef[j + parts], to_d(Q.at(j + parts, t)), a1);
       }
-      if (j < cnt) a0 = fma(coef[j], to_d(Q[(int64_t)j * n + s]), a0);
+      if (j < cnt) a0 = fma(coef[j], to_d(Q.at(j, t)), a0);
       acc = a0 + a1;
     }
     if (parts > 1) {
@@ -273,23 +281,21 @@ __device__ __forceinline__ void own_axpy(const XT* __restrict__ Q, int64_t n, in
 // |r| over the own rows is returned (valid in every thread).  Same thread
 // split as own_axpy; psum and psum2 are LDS scratch of kPB doubles each.
 template <typename XT>
-__device__ __forceinline__ double own_form(XT* __restrict__ Q, int64_t n, int64_t s_lo, int nown,
-                                           int i, const double* __restrict__ d,
+__device__ __forceinline__ double own_form(QView<XT> Q, int nown, int i,
+                                           const double* __restrict__ d,
                                            const double* __restrict__ z, double inv,
                                            const double* __restrict__ w1l, double* psum,
                                            double* psum2) {
   const int parts = nown >= kPB ? 1 : max(1, min(8, kPB / pow2_ceil(max(nown, 1))));
   const int span = kPB / parts;
   const int p = threadIdx.x / span, tl = threadIdx.x % span;
-  XT* qi = Q + (int64_t)i * n;
   double rmax = 0.0;
   for (int t0 = 0; t0 < nown; t0 += span) {
     const int t = t0 + tl;
     double ad = 0.0, az = 0.0;
     if (t < nown) {
-      const int64_t s = s_lo + t;
       for (int j = p; j < i; j += parts) {
-        const double q = to_d(Q[(int64_t)j * n + s]);
+        const double q = to_d(Q.at(j, t));
         ad = fma(d[j], q, ad);
         az = fma(z[j], q, az);
       }
@@ -311,7 +317,7 @@ __device__ __forceinline__ double own_form(XT* __restrict__ Q, int64_t n, int64_
     }
     if (p == 0 && t < nown) {
       const XT qx = from_d<XT>((w1l[t] - ad) * inv);
-      qi[s_lo + t] = qx;
+      Q.at(i, t) = qx;
       rmax = fmax(rmax, fabs(fma(z[i], to_d(qx), az)));
     }
   }
@@ -335,7 +341,9 @@ __device__ __forceinline__ void back_sub(Lsq& L, int cols) {
   }
 }
 
-template <typename VT, typename XT, int G>
+// QL: the block's basis rows live in LDS (dynamic shared memory, after the
+// two own-row vectors); otherwise in the global basis.
+template <typename VT, typename XT, int G, bool QL>
 __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
   using AT = XT;  // accumulation of the P^pi products inside GMRES
   constexpr int S = kWave / G;
@@ -356,8 +364,15 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
 
   __shared__ Lsq L;
   __shared__ Scal sc;
-  __shared__ double wl[kPMaxOwn];   // w of own rows
-  __shared__ double w1l[kPMaxOwn];  // w1 of own rows
+  extern __shared__ double dsm[];   // [ldq] w, [ldq] w1 of the own rows, then the basis rows
+  const int ldq = A.spb * kSlice;
+  double* wl = dsm;
+  double* w1l = dsm + ldq;
+  QView<XT> Qv;
+  if constexpr (QL)
+    Qv = QView<XT>{reinterpret_cast<XT*>(dsm + 2 * ldq), ldq};
+  else
+    Qv = QView<XT>{A.Q + s_lo, n};
   __shared__ double red[kPMaxW + 8];
   __shared__ double coef[kPMaxW + 1];
   __shared__ double psum[kPB];
@@ -381,7 +396,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
   auto explicit_resid = [&](int cols) -> bool {
     for (int j = threadIdx.x; j < cols; j += kPB) coef[j] = L.y[j];
     __syncthreads();
-    own_axpy<XT>(A.Q, n, s_lo, nown, cols, coef, 1.0, psum, [&](int t) { return A.Vb[s_lo + t]; },
+    own_axpy<XT>(Qv, nown, cols, coef, 1.0, psum, [&](int t) { return A.Vb[s_lo + t]; },
                  [&](int t, double v) { A.V[s_lo + t] = v; });
     if (!gbarrier(A.flags, A.ctl, ++epoch)) return false;
     {
@@ -521,15 +536,14 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
     for (;;) {
       // ---------------- [A] form Q_i; w = J Q_i; c = Q^T w
       {
-        XT* qi = A.Q + (int64_t)i * n;
         if (from_r) {
           const double inv = 1.0 / sc.beta;
           for (int64_t s = s_lo + threadIdx.x; s < v_hi; s += kPB)
-            qi[s] = from_d<XT>(A.r[s] * inv);
+            Qv.at(i, (int)(s - s_lo)) = from_d<XT>(A.r[s] * inv);
         } else {
           // second-pass correction of the previous step, applied now, and the
           // implicit residual of column i-1 from the same basis rows
-          impl_max = own_form<XT>(A.Q, n, s_lo, nown, i, L.d, L.z, sc.inv_eta, w1l, psum, psum2);
+          impl_max = own_form<XT>(Qv, nown, i, L.d, L.z, sc.inv_eta, w1l, psum, psum2);
         }
         // product: gather the complete source vector (r or w1), then scale
         const double inv_src = from_r ? 1.0 / sc.beta : sc.inv_eta;
@@ -549,7 +563,8 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
           if (s < n && g == 0) wl[s - s_lo] = wv;
         }
         __syncthreads();
-        own_dots<XT>(A.Q, n, i + 1, s_lo, nown, wl, MYPART, false);
+        __syncthreads();  // Q_i of the own rows complete before the projections
+        own_dots<XT>(Qv, i + 1, nown, wl, MYPART, false);
         if (threadIdx.x == 0 && !from_r) MYPART[i + 1] = impl_max;  // reduced with max
       }
       IG_BARRIER();
@@ -574,14 +589,14 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         }
       }
       // ---------------- [B] w1 = w - Q c; d = Q^T w1; sigma = ||w1||^2
-      own_axpy<XT>(A.Q, n, s_lo, nown, i + 1, L.c, -1.0, psum, [&](int t) { return wl[t]; },
+      own_axpy<XT>(Qv, nown, i + 1, L.c, -1.0, psum, [&](int t) { return wl[t]; },
                    [&](int t, double v) {
                      const XT vx = from_d<XT>(v);
                      A.w1[s_lo + t] = vx;
                      w1l[t] = to_d(vx);
                    });
       __syncthreads();
-      own_dots<XT>(A.Q, n, i + 1, s_lo, nown, w1l, MYPART, true);
+      own_dots<XT>(Qv, i + 1, nown, w1l, MYPART, true);
       IG_BARRIER();
       reduce_rows(PARTS, i + 2, 0u, red);
       if (threadIdx.x == 0) {
@@ -711,15 +726,27 @@ leave:
 template <typename VT, typename XT, int G>
 ig_status launch_persist(Mdp& d, const PArgs<VT, XT>& a, int nblocks, bool coop, hipStream_t s) {
   void* args[] = {(void*)&a};
+  // the block's basis rows go to LDS when they fit beside the static LDS
+  const size_t ldq = (size_t)a.spb * kSlice;
+  const size_t dyn_w = 2 * ldq * sizeof(double), dyn_q = (size_t)(a.W + 1) * ldq * sizeof(XT);
+  hipFuncAttributes fa{};
+  const void* kq = (const void*)k_persist<VT, XT, G, true>;
+  const void* kg = (const void*)k_persist<VT, XT, G, false>;
+  const bool ql = hipFuncGetAttributes(&fa, kq) == hipSuccess &&
+                  fa.sharedSizeBytes + dyn_w + dyn_q <= (size_t)d.max_lds;
+  (void)hipGetLastError();
+  const void* kern = ql ? kq : kg;
+  const size_t dyn = dyn_w + (ql ? dyn_q : 0);
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
+    (void)hipGetLastError();  // not needed on every runtime; the launch reports real failures
   ProfScope prof(d, KC_PERSIST, s);
   // A plain launch is used by the serving loop, which keeps every block of
   // all running solves co-resident by admission (cooperative launches are
   // serialised by the runtime).
   if (coop)
-    IG_HIP(hipLaunchCooperativeKernel((const void*)k_persist<VT, XT, G>, dim3(nblocks), dim3(kPB),
-                                      args, 0, s));
+    IG_HIP(hipLaunchCooperativeKernel(kern, dim3(nblocks), dim3(kPB), args, (unsigned)dyn, s));
   else
-    IG_HIP(hipLaunchKernel((const void*)k_persist<VT, XT, G>, dim3(nblocks), dim3(kPB), args, 0, s));
+    IG_HIP(hipLaunchKernel(kern, dim3(nblocks), dim3(kPB), args, dyn, s));
   return IG_OK;
 }
 

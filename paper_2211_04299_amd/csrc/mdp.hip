@@ -615,6 +615,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
   int coop = 0;
   IG_HIP(hipDeviceGetAttribute(&d->num_cu, hipDeviceAttributeMultiprocessorCount, d->device));
   IG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, d->device));
+  IG_HIP(hipDeviceGetAttribute(&d->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, d->device));
   d->coop = coop != 0;
   // uploads from the local staging must finish before it goes away
   if (!d->region) IG_HIP(hipDeviceSynchronize());
