@@ -599,44 +599,63 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
       own_dots<XT>(Qv, i + 1, nown, w1l, MYPART, true);
       IG_BARRIER();
       reduce_rows(PARTS, i + 2, 0u, red);
-      if (threadIdx.x == 0) {
-        sc.alg_bytes += A.b_japply + A.b_vec * (3.0 * (i + 1) + 4.0);
-        double dd = 0.0;
-        for (int j = 0; j <= i; ++j) {
-          L.d[j] = red[j];
-          dd = fma(red[j], red[j], dd);
+      // Givens update of column i on wave 0: the element-wise parts on its
+      // lanes (j <= i <= 63), the rotation and residual recurrences on lane 0
+      // with their operands loaded ahead of the dependent arithmetic
+      if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        double dj = 0.0;
+        if (lane <= i) {
+          dj = red[lane];
+          L.d[lane] = dj;
+          L.c[lane] += dj;  // column i of H: c + d
         }
+        const double dd = wave_sum(dj * dj);
         const double eta = sqrt(fmax(red[i + 1] - dd, 0.0));
-        // column i of H: c + d, with H(i+1, i) = eta; Givens update
-        double* h = L.c;
-        for (int j = 0; j <= i; ++j) h[j] += L.d[j];
-        h[i + 1] = eta;
-        for (int j = 0; j < i; ++j) {
-          const double t = L.cs[j] * h[j] + L.sn[j] * h[j + 1];
-          h[j + 1] = -L.sn[j] * h[j] + L.cs[j] * h[j + 1];
-          h[j] = t;
-        }
-        const double rr = hypot(h[i], h[i + 1]);
-        double cs = 1.0, sn = 0.0;
-        if (rr > 0.0) {
-          cs = h[i] / rr;
-          sn = h[i + 1] / rr;
-        }
-        L.cs[i] = cs;
-        L.sn[i] = sn;
-        h[i] = rr;
-        L.g[i + 1] = -sn * L.g[i];
-        L.g[i] = cs * L.g[i];
-        for (int j = 0; j <= i; ++j) L.R[i * (kPMaxW + 1) + j] = h[j];
-        const double rho = fabs(L.g[i + 1]);
-        {  // residual of this column's iterate in basis coordinates
-          double v = L.g[i + 1];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) {
+          double* h = L.c;
+          h[i + 1] = eta;
+          double hj = h[0];
+#pragma unroll 4
+          for (int j = 0; j < i; ++j) {  // previous rotations
+            const double c = L.cs[j], sn = L.sn[j], h1 = h[j + 1];
+            h[j] = c * hj + sn * h1;
+            hj = -sn * hj + c * h1;
+          }
+          const double rr = hypot(hj, eta);
+          double cs = 1.0, sn = 0.0;
+          if (rr > 0.0) {
+            cs = hj / rr;
+            sn = eta / rr;
+          }
+          L.cs[i] = cs;
+          L.sn[i] = sn;
+          h[i] = rr;
+          const double gi = L.g[i];
+          L.g[i + 1] = -sn * gi;
+          L.g[i] = cs * gi;
+          // residual of this column's iterate in basis coordinates
+          double v = -sn * gi;
+#pragma unroll 4
           for (int j = i; j >= 0; --j) {
-            L.z[j + 1] = L.cs[j] * v;
-            v = -L.sn[j] * v;
+            const double c = L.cs[j], snj = L.sn[j];
+            L.z[j + 1] = c * v;
+            v = -snj * v;
           }
           L.z[0] = v;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane <= i) L.R[i * (kPMaxW + 1) + lane] = L.c[lane];
+      }
+      if (threadIdx.x == 0) {
+        sc.alg_bytes += A.b_japply + A.b_vec * (3.0 * (i + 1) + 4.0);
+        const double eta = L.c[i + 1];
+        const double rho = fabs(L.g[i + 1]);
         sc.eta = eta;
         sc.inv_eta = eta > 0.0 ? 1.0 / eta : 0.0;
         sc.rho = rho;
