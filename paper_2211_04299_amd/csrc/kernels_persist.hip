@@ -129,11 +129,22 @@ __device__ void reduce_rows(const double* __restrict__ part, int cnt, unsigned m
     const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
     const bool mx = (c0 == 0 && c < 32 && ((maxmask >> c) & 1u)) || c0 + c == maxcol;
     double acc = 0.0;
-    if (c0 + c < cnt)
-      for (int b = q; b < nb; b += 16) {
-        const double x = part[(int64_t)b * kPStride + c0 + c];
-        acc = mx ? fmax(acc, x) : acc + x;
+    if (c0 + c < cnt) {
+      // the loads of up to 128 blocks are issued before the first add (one
+      // round trip each 128 blocks); the sum still runs over b = q, q+16,
+      // ... in that order
+      for (int b0 = 0; b0 < nb; b0 += 128) {
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int b = b0 + q + 16 * k;
+          x[k] = b < nb ? part[(int64_t)b * kPStride + c0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (b0 + q + 16 * k < nb) acc = mx ? fmax(acc, x[k]) : acc + x[k];
       }
+    }
     seg[q][c] = acc;
     __syncthreads();
     if (threadIdx.x < 64 && c0 + threadIdx.x < cnt) {
