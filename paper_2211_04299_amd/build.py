@@ -20,7 +20,8 @@ OBJ = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 SOURCES = ["mdp.hip", "solver.hip", "kernels_sparse.hip", "kernels_krylov.hip", "kernels_dense.hip",
-           "kernels_persist.hip", "server.hip"]
+           "kernels_persist.hip", "server.hip",
+           "convert.hip"]
 
 HIPFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

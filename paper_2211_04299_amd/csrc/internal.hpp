@@ -193,6 +193,26 @@ void launch_form_qi(Mdp& d, bool fp32, int c, const void* w1, hipStream_t s);
 void launch_dots(Mdp& d, bool fp32, int cnt, const void* v, bool givens, bool with_impl,
                  hipStream_t s);
 // w1 = y - sum_{j<cnt} gs->h_j Q_j
+// device conversion of CSR entries into the sliced-ELL image (layout from
+// the host; see convert.hip)
+struct ConvArgs {
+  int64_t n;
+  int m;
+  const int64_t* rp;
+  const int32_t* col;
+  const void* val;
+  const uint8_t* adm_t;  // [m][n] or null
+  const int64_t* off;
+  const int32_t* width;
+  const int32_t* mcnt;
+  int32_t* scol;
+  void* sval;
+  int validate;
+  double sum_tol;
+  unsigned long long* err;  // 5 counters, zeroed by the caller
+};
+void launch_fill_sell(const ConvArgs& c, ig_dtype val_type, ig_dtype store, hipStream_t s);
+
 // one Arnoldi step's orthogonalisation (after the J-apply): fused two-pass
 // form for columns up to gs_fused_max, else the four-kernel sequence
 // Horner step of the Neumann preconditioner: y = x*sx + gamma*(P^pi z)*sz,

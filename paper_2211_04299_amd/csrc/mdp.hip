@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <memory>
@@ -250,8 +251,10 @@ FillOut fill_sell_in(ig_dtype store, int64_t n, int m, const int64_t* rp, const 
   }
 }
 
+// zero fill on the handle's stream; plain handles wait for it
 ig_status dzero(Mdp* d, void* dst, size_t bytes) {
-  const hipError_t e = d->region ? hipMemsetAsync(dst, 0, bytes, d->stream) : hipMemset(dst, 0, bytes);
+  hipError_t e = hipMemsetAsync(dst, 0, bytes, d->stream);
+  if (e == hipSuccess && !d->region) e = hipStreamSynchronize(d->stream);
   return e == hipSuccess ? IG_OK : fail(IG_E_DEVICE, "hipMemset failed");
 }
 
@@ -444,17 +447,6 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     if (bad_rows)
       return fail(IG_E_INVALID, "row_ptr must be nondecreasing and every admissible (s,a) row non-empty");
     const int64_t nnz = rp[R];
-    std::vector<int32_t> col_h = to_host(desc->col, (size_t)nnz, ondev, &st);
-    if (st) return st;
-    const int32_t* col = ondev ? col_h.data() : desc->col;
-    std::vector<uint8_t> val_h;
-    const void* valp = desc->val;
-    if (ondev) {
-      val_h.resize((size_t)nnz * dtype_bytes(desc->val_type));
-      if (hipMemcpy(val_h.data(), desc->val, val_h.size(), hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(IG_E_DEVICE, "copy of device values failed");
-      valp = val_h.data();
-    }
 
     // per 64-state slice: width (longest admissible row) and action blocks
     // (1 + largest admissible action index of its states)
@@ -476,14 +468,41 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       maxlen = std::max(maxlen, w);
     }
     if (maxlen > n) return fail(IG_E_INVALID, "a row has more entries than states");
+    // The entries (O(nnz)) are converted on the device for serving, for
+    // device-resident inputs and for large MDPs; only the per-slice layout
+    // (O(rows)) is computed here.  The device's repeated-column test is
+    // quadratic in the row length, so host inputs with long rows stay on the
+    // host.  IG_CONVERT=host|device forces a route.
+    bool dev_route = d->region != nullptr || ondev || nnz >= ((int64_t)1 << 22);
+    if (validate && maxlen > 256 && !ondev) dev_route = false;
+    if (const char* ev = std::getenv("IG_CONVERT")) {
+      if (!std::strcmp(ev, "host")) dev_route = false;
+      if (!std::strcmp(ev, "device")) dev_route = true;
+    }
+    std::vector<int32_t> col_h;
+    std::vector<uint8_t> val_h;
+    const int32_t* col = desc->col;
+    const void* valp = desc->val;
+    if (ondev && !dev_route) {
+      col_h = to_host(desc->col, (size_t)nnz, ondev, &st);
+      if (st) return st;
+      col = col_h.data();
+      val_h.resize((size_t)nnz * dtype_bytes(desc->val_type));
+      if (hipMemcpy(val_h.data(), desc->val, val_h.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(IG_E_DEVICE, "copy of device values failed");
+      valp = val_h.data();
+    }
     int64_t tot = 0, totp = 0;
     for (int64_t b = 0; b < ns; ++b) {
       tot += (int64_t)mblk[b] * width[b] * kSlice;
       totp += (int64_t)width[b] * kSlice;
     }
-    const size_t need = Staging::round64((size_t)R * 8) + Staging::round64((size_t)tot * 4) +
-                        Staging::round64((size_t)tot * d->vb) + 2 * Staging::round64((size_t)ns * 8) +
-                        2 * Staging::round64((size_t)ns * 4) + adm_bytes;
+    const size_t ell_host = dev_route ? 0
+                                      : Staging::round64((size_t)tot * 4) +
+                                            Staging::round64((size_t)tot * d->vb);
+    const size_t need = Staging::round64((size_t)R * 8) + ell_host +
+                        2 * Staging::round64((size_t)ns * 8) + 2 * Staging::round64((size_t)ns * 4) +
+                        adm_bytes;
     if (ig_status e = stage_get(need)) return e;
     if (ig_status e = transpose_costs()) return e;
     transpose_adm();
@@ -491,8 +510,8 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     int64_t* offp = hs.take<int64_t>((size_t)ns);
     int32_t* wid = hs.take<int32_t>((size_t)ns);
     int32_t* mc = hs.take<int32_t>((size_t)ns);
-    int32_t* scol = hs.take<int32_t>((size_t)tot);
-    void* sval = hs.take<char>((size_t)tot * d->vb);
+    int32_t* scol = dev_route ? nullptr : hs.take<int32_t>((size_t)tot);
+    void* sval = dev_route ? nullptr : hs.take<char>((size_t)tot * d->vb);
     for (int64_t b = 0, t = 0, tp = 0; b < ns; ++b) {
       off[b] = t;
       offp[b] = tp;
@@ -502,7 +521,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       tp += (int64_t)width[b] * kSlice;
     }
     FillOut F;
-    switch (desc->val_type) {
+    if (!dev_route) switch (desc->val_type) {
       case IG_FP64:
         F = fill_sell_in<double>(d->store, n, m, rp, col, valp, wid, mc, off, adm, scol, sval, validate,
                                  sum_tol);
@@ -516,12 +535,18 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
                                  sum_tol);
         break;
     }
-    if (F.bad_col) return fail(IG_E_INVALID, "column index out of range");
-    if (F.bad_dup) return fail(IG_E_INVALID, "repeated column inside a row");
-    if (F.bad_p) return fail(IG_E_INVALID, "probabilities must lie in [0,1]");
-    if (F.bad_sum) return fail(IG_E_INVALID, "a transition row does not sum to 1");
-    if (validate && !(d->gamma * F.max_stored_sum < 1.0))
-      return fail(IG_E_INVALID, "gamma * (largest stored row sum) must be < 1");
+    // checks, in this order for both routes (device counts arrive below)
+    auto check = [&](const FillOut& F) -> ig_status {
+      if (F.bad_col) return fail(IG_E_INVALID, "column index out of range");
+      if (F.bad_dup) return fail(IG_E_INVALID, "repeated column inside a row");
+      if (F.bad_p) return fail(IG_E_INVALID, "probabilities must lie in [0,1]");
+      if (F.bad_sum) return fail(IG_E_INVALID, "a transition row does not sum to 1");
+      if (validate && !(d->gamma * F.max_stored_sum < 1.0))
+        return fail(IG_E_INVALID, "gamma * (largest stored row sum) must be < 1");
+      return IG_OK;
+    };
+    if (!dev_route)
+      if (ig_status e = check(F)) return e;
 
     d->nslices = ns;
     d->maxK = (int)maxlen;
@@ -534,12 +559,83 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         dmalloc(&d->width, (size_t)ns * 4) || dmalloc(&d->mcnt, (size_t)ns * 4) ||
         dmalloc(&d->pcol, (size_t)totp * 4) || dmalloc(&d->pval, (size_t)totp * d->vb))
       return IG_E_NOMEM;
-    if (ig_status e = upload(d, d->col, scol, (size_t)tot * 4)) return e;
-    if (ig_status e = upload(d, d->val, sval, (size_t)tot * d->vb)) return e;
+    if (!dev_route) {
+      if (ig_status e = upload(d, d->col, scol, (size_t)tot * 4)) return e;
+      if (ig_status e = upload(d, d->val, sval, (size_t)tot * d->vb)) return e;
+    }
     if (ig_status e = upload(d, d->off, off, (size_t)ns * 8)) return e;
     if (ig_status e = upload(d, d->offp, offp, (size_t)ns * 8)) return e;
     if (ig_status e = upload(d, d->width, wid, (size_t)ns * 4)) return e;
     if (ig_status e = upload(d, d->mcnt, mc, (size_t)ns * 4)) return e;
+    if (dev_route) {
+      // raw CSR on the device (the caller's arrays when they are already
+      // there), then the conversion kernel and its counts
+      if (adm_t) {
+        if (dmalloc(&d->adm, (size_t)R)) return IG_E_NOMEM;
+        if (ig_status e = upload(d, d->adm, adm_t, (size_t)R)) return e;
+      }
+      const size_t vin = dtype_bytes(desc->val_type);
+      int64_t* rp_d = nullptr;
+      int32_t* col_d = nullptr;
+      char* val_d = nullptr;
+      unsigned long long* err_d = nullptr;
+      const bool temp = d->region == nullptr;  // plain allocations to free here
+      auto free_temp = [&]() {
+        if (!temp) return;
+        if (!ondev) {
+          if (rp_d) (void)hipFree(rp_d);
+          if (col_d) (void)hipFree(col_d);
+          if (val_d) (void)hipFree(val_d);
+        }
+        if (err_d) (void)hipFree(err_d);
+      };
+      if (ondev) {
+        rp_d = const_cast<int64_t*>(desc->row_ptr);
+        col_d = const_cast<int32_t*>(desc->col);
+        val_d = (char*)const_cast<void*>(desc->val);
+      } else if (dmalloc(&rp_d, ((size_t)R + 1) * 8) || dmalloc(&col_d, (size_t)nnz * 4) ||
+                 dmalloc(&val_d, (size_t)nnz * vin)) {
+        free_temp();
+        return fail(IG_E_NOMEM, "device staging of the CSR arrays");
+      }
+      if (dmalloc(&err_d, 5 * sizeof(unsigned long long))) {
+        free_temp();
+        return fail(IG_E_NOMEM, "device staging of the CSR arrays");
+      }
+      ig_status e = IG_OK;
+      if (!ondev) {
+        e = upload(d, rp_d, desc->row_ptr, ((size_t)R + 1) * 8);
+        if (!e) e = upload(d, col_d, desc->col, (size_t)nnz * 4);
+        if (!e) e = upload(d, val_d, desc->val, (size_t)nnz * vin);
+      }
+      if (!e) e = dzero(d, err_d, 5 * sizeof(unsigned long long));
+      // plain mode copied with blocking calls; order them before the kernel
+      if (!e && !d->region && hipDeviceSynchronize() != hipSuccess)
+        e = fail(IG_E_DEVICE, "device staging of the CSR arrays");
+      if (!e) {
+        ConvArgs c{n, m, rp_d, col_d, val_d, d->adm, d->off, d->width, d->mcnt, d->col, d->val,
+                   validate ? 1 : 0, sum_tol, err_d};
+        launch_fill_sell(c, desc->val_type, d->store, d->stream);
+        if (hipGetLastError() != hipSuccess) e = fail(IG_E_DEVICE, "conversion kernel launch failed");
+      }
+      unsigned long long cnt[5] = {0, 0, 0, 0, 0};
+      if (!e) {
+        const hipError_t h = d->region ? hipStreamSynchronize(d->stream) : hipDeviceSynchronize();
+        if (h != hipSuccess || hipMemcpy(cnt, err_d, sizeof cnt, hipMemcpyDeviceToHost) != hipSuccess)
+          e = fail(IG_E_DEVICE, "device conversion failed");
+      }
+      free_temp();
+      if (e) return e;
+      FillOut G;
+      G.bad_col = cnt[0] ? 1 : 0;
+      G.bad_dup = cnt[1] ? 1 : 0;
+      G.bad_p = cnt[2] ? 1 : 0;
+      G.bad_sum = cnt[3] ? 1 : 0;
+      double mss;
+      std::memcpy(&mss, &cnt[4], 8);
+      G.max_stored_sum = mss;
+      if (ig_status e2 = check(G)) return e2;
+    }
     if (ig_status e = dzero(d, d->pcol, (size_t)totp * 4)) return e;
     if (ig_status e = dzero(d, d->pval, (size_t)totp * d->vb)) return e;
 
@@ -597,7 +693,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       dmalloc(&d->pctl, sizeof(PCtl)))
     return IG_E_NOMEM;
   if (ig_status e = upload(d, d->cost, cost_t, (size_t)R * 8)) return e;
-  if (adm_t) {
+  if (adm_t && !d->adm) {
     if (dmalloc(&d->adm, (size_t)R)) return IG_E_NOMEM;
     if (ig_status e = upload(d, d->adm, adm_t, (size_t)R)) return e;
   }
@@ -716,6 +812,10 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
     }
     b += round256(tot * 4) + round256(tot * vb) + 2 * round256(ns * 8) + 2 * round256(ns * 4) +
          round256(totp * 4) + round256(totp * vb);
+    // raw CSR staging of the device conversion (region handles use it)
+    const int64_t nnz = rp[R];
+    b += round256((R + 1) * 8) + round256(nnz * 4) + round256(nnz * dtype_bytes(desc->val_type)) +
+         round256(5 * sizeof(unsigned long long));
   } else {
     b += round256((size_t)R * n * vb);
   }

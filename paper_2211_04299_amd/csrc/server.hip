@@ -165,6 +165,7 @@ ig_status prepare(Server& S, Req* r, hipStream_t ps, PinnedStage* stage) {
   d->stage = stage;
   d->own_host_mirrors = false;
   if (ig_status e = create_in(&r->desc, d.get())) {
+    (void)hipStreamSynchronize(ps);  // copies out of the staging may be in flight
     release_handle(d.get());
     return e;
   }

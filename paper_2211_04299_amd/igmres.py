@@ -270,11 +270,41 @@ def _desc(mdp, store, validate):
     return d, keep
 
 
-def mdp_create(mdp, store: str = "fp64", validate: bool = True, stream=None) -> Mdp:
+def _desc_device(mdp, store, validate):
+    """Description of a CSR MDP whose arrays are device tensors (row_ptr
+    int64, col int32, val float64/float32/int16-or-uint16 bf16 patterns,
+    cost float64, adm uint8/bool or None)."""
+    import torch
+    if mdp.fmt != "csr":
+        raise ValueError("device inputs are taken for CSR MDPs")
+    d = MdpDesc()
+    d.n, d.m, d.gamma = mdp.n, mdp.m, float(mdp.gamma)
+    d.fmt = IG_FMT_CSR
+    vt = {torch.float64: IG_FP64, torch.float32: IG_FP32, torch.int16: IG_BF16,
+          torch.uint16: IG_BF16, torch.bfloat16: IG_BF16}[mdp.val.dtype]
+    for name, t, dt in (("row_ptr", mdp.row_ptr, torch.int64), ("col", mdp.col, torch.int32),
+                        ("cost", mdp.cost, torch.float64)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous device tensor of {dt}")
+    d.row_ptr, d.col, d.val, d.cost = (mdp.row_ptr.data_ptr(), mdp.col.data_ptr(),
+                                       mdp.val.data_ptr(), mdp.cost.data_ptr())
+    d.val_type = vt
+    d.store = DTYPES[store]
+    d.inputs_on_device = 1
+    d.validate = int(validate)
+    adm = getattr(mdp, "adm", None)
+    if adm is not None:
+        d.admissible = adm.data_ptr()
+    return d, [mdp]
+
+
+def mdp_create(mdp, store: str = "fp64", validate: bool = True, stream=None,
+               inputs_on_device: bool = False) -> Mdp:
     """Create a device MDP from a synth.MDP-like object with host arrays
     (fmt "csr": row_ptr/col/val; "dense": P).  `mdp.val` / `mdp.P` may be
-    float64, float32 or uint16 (bf16 bit patterns)."""
-    d, keep = _desc(mdp, store, validate)
+    float64, float32 or uint16 (bf16 bit patterns).  inputs_on_device: the
+    CSR arrays, costs and mask are device tensors instead."""
+    d, keep = (_desc_device if inputs_on_device else _desc)(mdp, store, validate)
     h = C.c_void_p()
     _check(_lib.mdp_create(C.byref(d), stream, C.byref(h)), "mdp_create")
     del keep
