@@ -288,7 +288,10 @@ typedef struct {
   int64_t submitted, completed, failed;
   int32_t queued, preparing, ready, running;
   int32_t peak_running;   /* most solves seen running at once                */
-  int32_t xcd_units_cap;  /* co-residency budget (workgroups per XCD)        */
+  int32_t xcd_units_cap;  /* co-residency budget (workgroups per XCD): one CU
+                             per XCD less than the device has, so that the
+                             preparation kernels of new requests find room;
+                             a wider solve runs alone                         */
   size_t arena_bytes, arena_used, arena_peak;
 } ig_server_info;
 

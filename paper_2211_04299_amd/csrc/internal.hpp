@@ -55,7 +55,9 @@ struct PinnedStage {
   char* buf = nullptr;
   size_t cap = 0;
   std::vector<char*> retired;
+  hipEvent_t ev[2] = {nullptr, nullptr};  // the bounce halves' last copies
   char* get(size_t need);  // nullptr if the allocation fails
+  bool events();           // creates ev on first use; false on failure
   void release();
 };
 
@@ -207,6 +209,7 @@ struct ConvArgs {
   const int32_t* mcnt;
   int32_t* scol;
   void* sval;
+  int maxK;  // longest stored row (the largest slice width)
   int validate;
   double sum_tol;
   unsigned long long* err;  // 5 counters, zeroed by the caller

@@ -124,6 +124,34 @@ ig_status upload(Mdp* d, void* dst, const void* src, size_t bytes) {
   return e == hipSuccess ? IG_OK : fail(IG_E_DEVICE, "host to device copy failed");
 }
 
+// Host -> device copy of caller memory through a pinned double buffer on
+// the handle's stream: the memcpy of one chunk overlaps the DMA of the
+// previous one.  Pageable copies issued by several threads at once reach
+// well under the link's rate; staged ones reach it.
+struct Bounce {
+  char* buf = nullptr;  // 2 * half pinned bytes
+  size_t half = 0;
+  hipEvent_t* ev = nullptr;
+  int h = 0;
+  bool used[2] = {false, false};
+  ig_status put(hipStream_t s, void* dst, const void* src, size_t bytes) {
+    for (size_t done = 0; done < bytes;) {
+      const size_t c = std::min(half, bytes - done);
+      if (used[h] && hipEventSynchronize(ev[h]) != hipSuccess)
+        return fail(IG_E_DEVICE, "staged copy failed");
+      std::memcpy(buf + h * half, (const char*)src + done, c);
+      if (hipMemcpyAsync((char*)dst + done, buf + h * half, c, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipEventRecord(ev[h], s) != hipSuccess)
+        return fail(IG_E_DEVICE, "staged copy failed");
+      used[h] = true;
+      h ^= 1;
+      done += c;
+    }
+    return IG_OK;
+  }
+};
+constexpr size_t kBounceHalf = (size_t)8 << 20;
+
 // Bump allocation inside the host staging buffer of one create.
 struct Staging {
   char* base = nullptr;
@@ -474,7 +502,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     // quadratic in the row length, so host inputs with long rows stay on the
     // host.  IG_CONVERT=host|device forces a route.
     bool dev_route = d->region != nullptr || ondev || nnz >= ((int64_t)1 << 22);
-    if (validate && maxlen > 256 && !ondev) dev_route = false;
+    if (validate && maxlen > 128 && !ondev) dev_route = false;
     if (const char* ev = std::getenv("IG_CONVERT")) {
       if (!std::strcmp(ev, "host")) dev_route = false;
       if (!std::strcmp(ev, "device")) dev_route = true;
@@ -500,9 +528,11 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     const size_t ell_host = dev_route ? 0
                                       : Staging::round64((size_t)tot * 4) +
                                             Staging::round64((size_t)tot * d->vb);
+    // serving (pinned staging) bounces the raw arrays of the device route
+    const bool bounce = dev_route && d->stage && !ondev;
     const size_t need = Staging::round64((size_t)R * 8) + ell_host +
                         2 * Staging::round64((size_t)ns * 8) + 2 * Staging::round64((size_t)ns * 4) +
-                        adm_bytes;
+                        adm_bytes + (bounce ? 2 * kBounceHalf : 0);
     if (ig_status e = stage_get(need)) return e;
     if (ig_status e = transpose_costs()) return e;
     transpose_adm();
@@ -510,6 +540,13 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     int64_t* offp = hs.take<int64_t>((size_t)ns);
     int32_t* wid = hs.take<int32_t>((size_t)ns);
     int32_t* mc = hs.take<int32_t>((size_t)ns);
+    Bounce bb;
+    if (bounce) {
+      if (!d->stage->events()) return fail(IG_E_DEVICE, "hipEventCreate failed");
+      bb.buf = hs.take<char>(2 * kBounceHalf);
+      bb.half = kBounceHalf;
+      bb.ev = d->stage->ev;
+    }
     int32_t* scol = dev_route ? nullptr : hs.take<int32_t>((size_t)tot);
     void* sval = dev_route ? nullptr : hs.take<char>((size_t)tot * d->vb);
     for (int64_t b = 0, t = 0, tp = 0; b < ns; ++b) {
@@ -603,7 +640,11 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         return fail(IG_E_NOMEM, "device staging of the CSR arrays");
       }
       ig_status e = IG_OK;
-      if (!ondev) {
+      if (bounce) {
+        e = bb.put(d->stream, rp_d, desc->row_ptr, ((size_t)R + 1) * 8);
+        if (!e) e = bb.put(d->stream, col_d, desc->col, (size_t)nnz * 4);
+        if (!e) e = bb.put(d->stream, val_d, desc->val, (size_t)nnz * vin);
+      } else if (!ondev) {
         e = upload(d, rp_d, desc->row_ptr, ((size_t)R + 1) * 8);
         if (!e) e = upload(d, col_d, desc->col, (size_t)nnz * 4);
         if (!e) e = upload(d, val_d, desc->val, (size_t)nnz * vin);
@@ -614,7 +655,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         e = fail(IG_E_DEVICE, "device staging of the CSR arrays");
       if (!e) {
         ConvArgs c{n, m, rp_d, col_d, val_d, d->adm, d->off, d->width, d->mcnt, d->col, d->val,
-                   validate ? 1 : 0, sum_tol, err_d};
+                   (int)maxlen, validate ? 1 : 0, sum_tol, err_d};
         launch_fill_sell(c, desc->val_type, d->store, d->stream);
         if (hipGetLastError() != hipSuccess) e = fail(IG_E_DEVICE, "conversion kernel launch failed");
       }
@@ -735,7 +776,19 @@ char* PinnedStage::get(size_t need) {
   return buf;
 }
 
+bool PinnedStage::events() {
+  for (hipEvent_t& e : ev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+      return false;
+    }
+  return true;
+}
+
 void PinnedStage::release() {
+  for (hipEvent_t& e : ev)
+    if (e) (void)hipEventDestroy(e), e = nullptr;
   for (char* p : retired) (void)hipHostFree(p);
   retired.clear();
   if (buf) (void)hipHostFree(buf);
@@ -798,6 +851,7 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
     const int m = desc->m;
     const int64_t ns = (n + kSlice - 1) / kSlice;
     int64_t tot = 0, totp = 0;
+#pragma omp parallel for reduction(+ : tot, totp)
     for (int64_t sl = 0; sl < ns; ++sl) {
       int64_t w = 0;
       int mb = 0;

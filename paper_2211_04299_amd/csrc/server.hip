@@ -194,7 +194,10 @@ ig_status prepare(Server& S, Req* r, hipStream_t ps, PinnedStage* stage) {
     return e;
   }
   int want = r->p.blocks;
-  if (want <= 0) want = (int)((d->nslices + S.cfg.block_slices - 1) / S.cfg.block_slices);
+  if (want <= 0) {
+    want = (int)((d->nslices + S.cfg.block_slices - 1) / S.cfg.block_slices);
+    want = std::min(want, 8 * S.units_cap);  // runs beside others when the shape allows
+  }
   r->p.blocks = std::max(1, want);
   r->blocks = persistent_grid(*d, r->p.blocks);
   r->units = (r->blocks + 7) / 8;
@@ -366,7 +369,10 @@ void sched_loop(Server* Sp) {
       while (k < ns && S.slots[k].req) ++k;
       if (k == ns) break;
       Req* r = S.ready.begin()->second;
-      if (S.units_used + r->units > S.units_cap) break;
+      // within the budget; a solve wider than it runs alone (on up to every CU)
+      const bool fits = S.units_used + r->units <= S.units_cap ||
+                        (S.units_used == 0 && r->units <= std::max(1, S.num_cu / 8));
+      if (!fits) break;
       S.ready.erase(S.ready.begin());
       S.slots[k].req = r;
       S.units_used += r->units;
@@ -438,7 +444,10 @@ ig_status srv_create(const ig_server_config* cfg, ig_server_t* out) {
   if (hipSetDevice(cfg->device) != hipSuccess) return fail(IG_E_DEVICE, "hipSetDevice failed");
   if (hipDeviceGetAttribute(&S.num_cu, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess)
     return fail(IG_E_DEVICE, "device query failed");
-  S.units_cap = std::max(1, S.num_cu / 8);
+  // one CU per XCD stays outside the budget: the conversion and fill
+  // kernels of requests being prepared run there instead of waiting for a
+  // running solve to end
+  S.units_cap = std::max(1, S.num_cu / 8 - 1);
   if (hipMalloc((void**)&S.base, cfg->hbm_budget) != hipSuccess) {
     (void)hipGetLastError();
     return fail(IG_E_NOMEM, "hipMalloc of the serving arena failed");
