@@ -16,8 +16,13 @@ saturated throughput with every request queued at once, then p50/p99
 latency under Poisson arrivals at 0.8x that throughput, beside the same
 requests solved one at a time by the plain FP64 path).
 
+Also reported: per-solve device time p50/p90, the upload (mdp_create)
+time, and under "compare" the same workload by exact-evaluation PI and by
+OPI with 20 sweeps (FP64 workloads) or with FP64 storage and arithmetic
+(mixed workloads), each timed from V0 = 0 to the same tolerance.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c4|c3|c5]
-                    [--serve-requests R] [--no-serving]
+                    [--serve-requests R] [--no-serving] [--no-compare]
 """
 import argparse
 import hashlib
@@ -68,6 +73,49 @@ def per_launch_bytes(info, cls, fp32):
     if cls == "residual":
         return nnz_pi * entry + n * 8 * 3
     return None  # classes whose bytes depend on the step (persistent, Gram-Schmidt)
+
+
+def timed_solves(h, fn, V, pi, params, runs, torch):
+    """Wall time of `runs` solves from V0 = 0 (synchronised each), with the
+    last solve's counts."""
+    ts, st = [], None
+    for _ in range(runs):
+        V.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = fn(V, pi, params)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return {"ms_p50": round(float(np.median(ts)), 4), "ms_p90": round(float(np.percentile(ts, 90)), 4),
+            "runs": runs, "outer": st["outer"], "inner": st["inner"], "res_inf": st["res_inf"],
+            "converged": st["converged"]}
+
+
+def comparisons(igmres, torch, mdp, wl, restart, igmres_ms, runs):
+    """The same workload by the other methods (sparse FP64: exact-evaluation
+    PI and OPI with 20 sweeps) or the other precision (mixed workloads: FP64
+    storage and arithmetic), each from V0 = 0 to the same tolerance."""
+    out = {}
+    dev = torch.device("cuda:0")
+    V = torch.zeros(mdp.n, dtype=torch.float64, device=dev)
+    pi = torch.zeros(mdp.n, dtype=torch.int32, device=dev)
+    if wl["mode"] == "fp64":
+        with igmres.mdp_create(mdp, store="fp64") as h:
+            p = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8, mode="fp64")
+            out["pi"] = timed_solves(h, h.pi_solve, V, pi, p, runs, torch)
+            p = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8, mode="fp64", opi_sweeps=20)
+            out["opi20"] = timed_solves(h, h.opi_solve, V, pi, p, runs, torch)
+        for k in ("pi", "opi20"):
+            out[k]["igmres_pi_speedup"] = round(out[k]["ms_p50"] / igmres_ms, 2)
+    else:
+        t0 = time.perf_counter()
+        with igmres.mdp_create(mdp, store="fp64") as h:
+            create = (time.perf_counter() - t0) * 1e3
+            p = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8, mode="fp64")
+            out["fp64"] = timed_solves(h, h.igmres_pi_solve, V, pi, p, runs, torch)
+            out["fp64"]["create_ms"] = round(create, 1)
+        out["fp64"]["mixed_speedup"] = round(out["fp64"]["ms_p50"] / igmres_ms, 2)
+    return out
 
 
 def cpu_baseline(mdp, restart, budget_s=12.0):
@@ -213,6 +261,8 @@ def main():
                     help="degree of the Neumann right preconditioner of the inner GMRES (stream engine)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip PI/OPI (FP64 workloads) or the FP64 run (mixed workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -258,7 +308,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     print("[bench] uploading", file=sys.stderr, flush=True)
+    t_up = time.perf_counter()
     h = igmres.mdp_create(mdp, store=wl["store"])
+    create_ms = (time.perf_counter() - t_up) * 1e3
     info = h.info()
     V = torch.zeros(mdp.n, dtype=torch.float64, device=dev)
     pi = torch.zeros(mdp.n, dtype=torch.int32, device=dev)
@@ -312,6 +364,16 @@ def main():
                 "kernel": dom, "launches": dom_n, "avg_us": round(dom_avg_ms * 1e3, 3),
                 "alg_bytes_per_launch": b}
 
+    dev_ms = np.array([s["time_ms"] for s in stats])
+    cmp = None
+    if not args.no_compare:
+        print("[bench] comparisons", file=sys.stderr, flush=True)
+        runs = 5 if args.workload in ("c1", "c2", "c3") else 2
+        try:
+            cmp = comparisons(igmres, torch, mdp, wl, restart, ms_step, runs)
+        except igmres.IgError as e:  # reported, never fatal to the main line
+            cmp = {"error": str(e)}
+
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -335,6 +397,10 @@ def main():
                    else "stream (one launch per step)",
                    "precond_degree": args.precond},
         "time_to_tol_ms": round(ms_step, 4),
+        "solve_ms_p50": round(float(np.median(dev_ms)), 4),
+        "solve_ms_p90": round(float(np.percentile(dev_ms, 90)), 4),
+        "create_ms": round(create_ms, 2),
+        "compare": cmp,
         "solve": {"outer": st["outer"], "inner": st["inner"], "restarts": st["restarts"],
                   "explicit_residuals": st["explicit_residuals"], "res_inf": st["res_inf"],
                   "device_ms": round(st["time_ms"], 4),

@@ -26,6 +26,7 @@ namespace {
 
 constexpr int kJC = 8;       // dot products per sweep
 constexpr int kFinT = 1024;  // threads of the finishing kernel
+constexpr int kFinBatch = 16;  // partial rows each finishing thread loads at once
 
 template <typename XT>
 __device__ __forceinline__ const XT* qcol(const XT* Q, int64_t n, int j) {
@@ -398,9 +399,17 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
     const bool mx = c0 == 0 && c < 32 && ((maxmask >> c) & 1u);
     double acc = 0.0;
     if (c0 + c < cnt)
-      for (int b = q; b < nb; b += 16) {
-        const double x = part[(int64_t)b * stride + c0 + c];
-        acc = mx ? fmax(acc, x) : acc + x;
+      for (int b0 = q; b0 < nb; b0 += 16 * kFinBatch) {
+        // a batch of loads in flight before the (ordered) accumulation
+        double x[kFinBatch];
+#pragma unroll
+        for (int u = 0; u < kFinBatch; ++u) {
+          const int b = b0 + 16 * u;
+          x[u] = b < nb ? part[(int64_t)b * stride + c0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinBatch; ++u)
+          if (b0 + 16 * u < nb) acc = mx ? fmax(acc, x[u]) : acc + x[u];
       }
     seg[q][c] = acc;
     __syncthreads();
