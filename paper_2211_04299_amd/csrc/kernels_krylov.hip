@@ -193,6 +193,9 @@ __device__ __forceinline__ void load_row(const XT* __restrict__ Q, int64_t n, in
   for (int j = 0; j < JM; ++j) q[j] = Q[(int64_t)min(j, last) * n + s];
 }
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
 template <typename XT, int JM>
 __global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, int c,
                                                  const XT* __restrict__ w1,
@@ -200,10 +203,14 @@ __global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, 
                                                  const GivensState* __restrict__ gs,
                                                  const DevStatus* __restrict__ st,
                                                  double* __restrict__ part) {
-  __shared__ double dd[JM], zz[JM];
+  // The second-pass correction and the implicit residual accumulate in the
+  // basis type: with an FP32 basis their rounding is that of the stored
+  // vector they feed (the dot products below stay FP64).
+  using CT = XT;
+  __shared__ CT dd[JM], zz[JM];
   for (int j = threadIdx.x; j < JM; j += kBlock) {
-    dd[j] = j < c ? gs->h2[j] : 0.0;
-    zz[j] = j < c ? gs->z[j] : 0.0;
+    dd[j] = (CT)(j < c ? gs->h2[j] : 0.0);
+    zz[j] = (CT)(j < c ? gs->z[j] : 0.0);
   }
   __syncthreads();
   const double zc = gs->z[c];
@@ -228,22 +235,22 @@ __global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, 
     XT q[JM];
     load_row<XT, JM>(Q, n, c, s, q);
     const double ys = to_d(yv);
-    double corr0 = 0.0, corr1 = 0.0, r0 = 0.0, r1 = 0.0;
+    CT corr0 = 0, corr1 = 0, r0 = 0, r1 = 0;
 #pragma unroll
     for (int g = 0; g < JM; g += 8) {
       asm volatile("" ::: "memory");  // at most 8 coefficient pairs live
 #pragma unroll
       for (int j = g; j < g + 8; j += 2) {
-        corr0 = fma(dd[j], to_d(q[j]), corr0);
-        r0 = fma(zz[j], to_d(q[j]), r0);
-        corr1 = fma(dd[j + 1], to_d(q[j + 1]), corr1);
-        r1 = fma(zz[j + 1], to_d(q[j + 1]), r1);
+        corr0 = fma_t(dd[j], q[j], corr0);
+        r0 = fma_t(zz[j], q[j], r0);
+        corr1 = fma_t(dd[j + 1], q[j + 1], corr1);
+        r1 = fma_t(zz[j + 1], q[j + 1], r1);
       }
     }
-    const XT qx = from_d<XT>((to_d(wv) - (corr0 + corr1)) * inv);
+    const XT qx = from_d<XT>((to_d(wv) - to_d(corr0 + corr1)) * inv);
     if (c > 0) qc[s] = qx;
     const double qcs = c > 0 ? to_d(qx) : to_d(q0v);
-    const double rr = fabs(fma(zc, qcs, r0 + r1));
+    const double rr = fabs(fma(zc, qcs, to_d(r0 + r1)));
     rmax = c > 0 ? fmax(rmax, rr) : rmax;
 #pragma unroll
     for (int j = 0; j < JM; ++j) acc[j] = fma(to_d(q[j]), ys, acc[j]);
@@ -267,8 +274,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_b(const XT* __restrict__ Q, int64
                                                  const GivensState* __restrict__ gs,
                                                  const XT* __restrict__ y, XT* __restrict__ w1,
                                                  double* __restrict__ part) {
-  __shared__ double h[JM];
-  for (int j = threadIdx.x; j < JM; j += kBlock) h[j] = j < cnt ? gs->h[j] : 0.0;
+  // w1 accumulates in the basis type (the vector is stored in it); the dot
+  // products and the norm stay FP64
+  using CT = XT;
+  __shared__ CT h[JM];
+  for (int j = threadIdx.x; j < JM; j += kBlock) h[j] = (CT)(j < cnt ? -gs->h[j] : 0.0);
   __syncthreads();
   double acc[JM];
 #pragma unroll
@@ -283,19 +293,19 @@ __global__ __launch_bounds__(kBlock) void k_gs_b(const XT* __restrict__ Q, int64
     yn = y[min(s + stride, n - 1)];
     XT q[JM];
     load_row<XT, JM>(Q, n, cnt, s, q);
-    double a0 = to_d(yv), a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    CT a0 = yv, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
     for (int g = 0; g < JM; g += 8) {
       asm volatile("" ::: "memory");  // at most 8 coefficients live
 #pragma unroll
       for (int j = g; j < g + 8; j += 4) {
-        a0 = fma(-h[j], to_d(q[j]), a0);
-        a1 = fma(-h[j + 1], to_d(q[j + 1]), a1);
-        a2 = fma(-h[j + 2], to_d(q[j + 2]), a2);
-        a3 = fma(-h[j + 3], to_d(q[j + 3]), a3);
+        a0 = fma_t(h[j], q[j], a0);
+        a1 = fma_t(h[j + 1], q[j + 1], a1);
+        a2 = fma_t(h[j + 2], q[j + 2], a2);
+        a3 = fma_t(h[j + 3], q[j + 3], a3);
       }
     }
-    const XT wx = from_d<XT>((a0 + a1) + (a2 + a3));
+    const XT wx = (XT)((a0 + a1) + (a2 + a3));
     w1[s] = wx;
     const double wd = to_d(wx);
 #pragma unroll
