@@ -16,6 +16,10 @@ saturated throughput with every request queued at once, then p50/p99
 latency under Poisson arrivals at 0.8x that throughput, beside the same
 requests solved one at a time by the plain FP64 path).
 
+The roofline also carries the rate of a plain 1 GiB device copy measured
+in the same run ("copy_GBps", read + write bytes per second), context for
+the published peak.
+
 Also reported: per-solve device time p50/p90, the upload (mdp_create)
 time, and under "compare" the same workload by exact-evaluation PI and by
 OPI with 20 sweeps (FP64 workloads) or with FP64 storage and arithmetic
@@ -73,6 +77,26 @@ def per_launch_bytes(info, cls, fp32):
     if cls == "residual":
         return nnz_pi * entry + n * 8 * 3
     return None  # classes whose bytes depend on the step (persistent, Gram-Schmidt)
+
+
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Achievable HBM rate of a plain device-to-device copy on this GPU
+    (bytes read + written per second), the practical ceiling beside the
+    published peak."""
+    a = torch.empty(mib << 17, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbps
 
 
 def timed_solves(h, fn, V, pi, params, runs, torch):
@@ -359,10 +383,11 @@ def main():
             t = json.load(open(tfile))
             if t.get("kernel_source_hash") == kernel_source_hash():
                 traffic = t.get("hbm_bytes_per_launch")
+        cbw = copy_bandwidth(torch)
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": dom, "launches": dom_n, "avg_us": round(dom_avg_ms * 1e3, 3),
-                "alg_bytes_per_launch": b}
+                "alg_bytes_per_launch": b, "copy_GBps": round(cbw, 1)}
 
     dev_ms = np.array([s["time_ms"] for s in stats])
     cmp = None

@@ -5,6 +5,9 @@
 // length keeps rows 16-byte aligned), several loads in flight, and reduces
 // with shuffles; the block picks the (value, action)-lexicographic minimum.
 // Products with P^pi: one wavefront per state on row (s, pi(s)).
+#include <mutex>
+#include <unordered_map>
+
 #include "internal.hpp"
 
 namespace ig {
@@ -42,10 +45,12 @@ struct Vec<bf16> {
     return (double)__uint_as_float(bits);
   }
 };
-// 16-byte load of the row stream (a plain load: a non-temporal hint measured
-// slower on the dense rows)
+// 16-byte load of the row stream
 template <typename VV>
 __device__ __forceinline__ VV ldv(const VV* p) { return *p; }
+// the same with a non-temporal hint (rows read once per pass)
+template <typename VV>
+__device__ __forceinline__ VV ldv_nt(const VV* p) { return __builtin_nontemporal_load(p); }
 
 // sum_e row[e] * x[e] * scale over one row of length n, the whole wavefront
 // cooperating; AT is the accumulation type.  Result valid in every lane.
@@ -61,8 +66,8 @@ __device__ __forceinline__ AT dense_row_dot(const VT* __restrict__ row, int64_t 
     const int64_t nv = n / N;
     int64_t e = lane;
     for (; e + 3 * kWave < nv; e += 4 * kWave) {  // four 16-byte loads in flight per lane
-      const VV p0 = ldv(rv + e), p1 = ldv(rv + e + kWave), p2 = ldv(rv + e + 2 * kWave),
-               p3 = ldv(rv + e + 3 * kWave);
+      const VV p0 = ldv_nt(rv + e), p1 = ldv_nt(rv + e + kWave), p2 = ldv_nt(rv + e + 2 * kWave),
+               p3 = ldv_nt(rv + e + 3 * kWave);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         acc += (AT)Vec<VT>::at(p0, k) * (AT)(x[e * N + k] * scale);
@@ -72,7 +77,7 @@ __device__ __forceinline__ AT dense_row_dot(const VT* __restrict__ row, int64_t 
       }
     }
     for (; e < nv; e += kWave) {
-      const VV p0 = ldv(rv + e);
+      const VV p0 = ldv_nt(rv + e);
 #pragma unroll
       for (int k = 0; k < N; ++k) acc += (AT)Vec<VT>::at(p0, k) * (AT)(x[e * N + k] * scale);
     }
@@ -159,6 +164,189 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense(
   double v[4] = {pmax, psum, nonfin, chg};
   const int op[4] = {1, 0, 0, 0};
   store_partials<4>(v, op, part);
+}
+
+// Bellman pass with one wavefront per state: its action rows are streamed
+// RG at a time, U 16-byte loads per row and lane in flight, against one
+// load of V per element and group.  Each row's dot product is accumulated
+// in the same order as dense_row_dot, and the actions are visited in
+// increasing order (lowest index wins ties), as in k_bellman_dense.  Rows
+// must be 16-byte aligned (vec_ok).
+template <typename VT, int RG, int U>
+__global__ __launch_bounds__(kBlock) void k_bellman_dense4(
+    const VT* __restrict__ P, const double* __restrict__ cost, int m, int64_t n, double gamma,
+    const double* __restrict__ V, double* __restrict__ TV, double* __restrict__ Phi,
+    int32_t* __restrict__ pi, const int32_t* __restrict__ pi_old, double tie_abs,
+    double* __restrict__ cpi, double* __restrict__ part, const uint8_t* __restrict__ adm) {
+  constexpr int N = Vec<VT>::N;
+  using VV = typename Vec<VT>::T;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nv = n / N;
+  double pmax = 0.0, psum = 0.0, nonfin = 0.0, chg = 0.0;
+  for (int64_t s = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; s < n;
+       s += (int64_t)gridDim.x * kWpb) {
+    const int inc = pi_old ? pi_old[s] : -1;
+    double best = INFINITY, qinc = INFINITY;
+    int besta = m;
+    for (int a0 = 0; a0 < m; a0 += RG) {
+      bool use[RG];
+      const VV* rv[RG];
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        const int a = a0 + r;
+        use[r] = a < m && (!adm || adm[(int64_t)a * n + s]);
+        // an unused slot re-reads row a0 (in cache) and is dropped
+        rv[r] = reinterpret_cast<const VV*>(P + ((int64_t)s * m + (a < m ? a : a0)) * n);
+      }
+      double acc[RG];
+#pragma unroll
+      for (int r = 0; r < RG; ++r) acc[r] = 0.0;
+      int64_t e = lane;
+      for (; e + (U - 1) * kWave < nv; e += U * kWave) {
+        VV p[RG][U];
+#pragma unroll
+        for (int r = 0; r < RG; ++r)
+#pragma unroll
+          for (int u = 0; u < U; ++u) p[r][u] = ldv_nt(rv[r] + e + u * kWave);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          double x[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) x[u] = V[(e + u * kWave) * N + k];
+#pragma unroll
+          for (int r = 0; r < RG; ++r)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[r] += Vec<VT>::at(p[r][u], k) * x[u];
+        }
+      }
+      for (; e < nv; e += kWave) {
+        VV p[RG];
+#pragma unroll
+        for (int r = 0; r < RG; ++r) p[r] = ldv_nt(rv[r] + e);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double x0 = V[e * N + k];
+#pragma unroll
+          for (int r = 0; r < RG; ++r) acc[r] += Vec<VT>::at(p[r], k) * x0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o);
+      }
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        if (!use[r]) continue;
+        const int a = a0 + r;
+        const double q = cost[(int64_t)a * n + s] + gamma * acc[r];
+        if (!(q - q == 0.0)) nonfin += lane == 0 ? 1.0 : 0.0;
+        if (q < best) {
+          best = q;
+          besta = a;
+        }
+        if (a == inc) qinc = q;
+      }
+    }
+    if (besta >= m) {
+      besta = 0;
+      best = NAN;
+    }
+    int astar = besta;
+    double tv = best;
+    if (inc >= 0 && inc < m && qinc <= best + tie_abs) {
+      astar = inc;
+      tv = qinc;
+    }
+    if (lane == 0) {
+      const double phi = tv - V[s];
+      if (TV) TV[s] = tv;
+      Phi[s] = phi;
+      pi[s] = astar;
+      cpi[s] = cost[(int64_t)astar * n + s];
+      if (!(phi - phi == 0.0)) nonfin += 1.0;  // NaN/Inf in V itself
+      pmax = fmax(pmax, fabs(phi));
+      psum = fma(phi, phi, psum);
+      if (pi_old && astar != inc) chg += 1.0;
+    }
+  }
+  double v[4] = {pmax, psum, nonfin, chg};
+  const int op[4] = {1, 0, 0, 0};
+  store_partials<4>(v, op, part);
+}
+
+// y = x - gamma P^pi x with one wavefront on SG states at once: their SG
+// rows are streamed together (U 16-byte loads per row and lane in flight)
+// against one load of x per element.  Each row's dot product is
+// accumulated in the order of dense_row_dot.  Rows must be 16-byte aligned.
+template <typename VT, typename XT, typename AT, int SG, int U>
+__global__ __launch_bounds__(kBlock) void k_japply_dense_g(const VT* __restrict__ P, int m,
+                                                           int64_t n, AT gamma,
+                                                           const int32_t* __restrict__ pi,
+                                                           const XT* __restrict__ x,
+                                                           const double* __restrict__ eta,
+                                                           XT* __restrict__ y) {
+  constexpr int N = Vec<VT>::N;
+  using VV = typename Vec<VT>::T;
+  const int lane = threadIdx.x & (kWave - 1);
+  const XT scale = eta ? (XT)(1.0 / *eta) : (XT)1;
+  const int64_t nv = n / N;
+  const int64_t ng = (n + SG - 1) / SG;
+  for (int64_t gI = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; gI < ng;
+       gI += (int64_t)gridDim.x * kWpb) {
+    const int64_t s0 = gI * SG;
+    const VV* rv[SG];
+#pragma unroll
+    for (int r = 0; r < SG; ++r) {
+      const int64_t s = s0 + r < n ? s0 + r : s0;  // past the end: repeat row s0, dropped
+      rv[r] = reinterpret_cast<const VV*>(P + ((int64_t)s * m + pi[s]) * n);
+    }
+    AT acc[SG];
+#pragma unroll
+    for (int r = 0; r < SG; ++r) acc[r] = 0;
+    int64_t e = lane;
+    for (; e + (U - 1) * kWave < nv; e += U * kWave) {
+      VV p[SG][U];
+#pragma unroll
+      for (int r = 0; r < SG; ++r)
+#pragma unroll
+        for (int u = 0; u < U; ++u) p[r][u] = ldv_nt(rv[r] + e + u * kWave);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        AT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = (AT)(x[(e + u * kWave) * N + k] * scale);
+#pragma unroll
+        for (int r = 0; r < SG; ++r)
+#pragma unroll
+          for (int u = 0; u < U; ++u) acc[r] += (AT)Vec<VT>::at(p[r][u], k) * xv[u];
+      }
+    }
+    for (; e < nv; e += kWave) {
+      VV p[SG];
+#pragma unroll
+      for (int r = 0; r < SG; ++r) p[r] = ldv_nt(rv[r] + e);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const AT xv = (AT)(x[e * N + k] * scale);
+#pragma unroll
+        for (int r = 0; r < SG; ++r) acc[r] += (AT)Vec<VT>::at(p[r], k) * xv;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < SG; ++r) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o);
+    }
+    if (lane < SG && s0 + lane < n) {
+      AT a = acc[0];
+#pragma unroll
+      for (int r = 1; r < SG; ++r) a = lane == r ? acc[r] : a;
+      const int64_t s = s0 + lane;
+      const XT xs = x[s] * scale;
+      y[s] = (XT)((AT)xs - gamma * a);
+    }
+  }
 }
 
 template <typename VT, typename XT, typename AT>
@@ -260,6 +448,38 @@ inline int grid_states(int64_t n) {
 inline int grid_waves(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + kWpb - 1) / kWpb, kMaxBlocks));
 }
+// One wavefront per state in equal rounds: ceil(n / rounds) wavefronts,
+// with the fewest rounds for which all of them are resident at once
+// (`resident` blocks), so that no wave starts a late, mostly idle round.
+inline int grid_rounds(int64_t n, int resident) {
+  const int64_t cap = (int64_t)std::min(std::max(1, resident), kMaxBlocks) * kWpb;
+  const int64_t rounds = (n + cap - 1) / cap;
+  const int64_t waves = (n + rounds - 1) / rounds;
+  return (int)std::max<int64_t>(1, (waves + kWpb - 1) / kWpb);
+}
+
+// blocks of a kernel resident on the whole device (the per-CU occupancy
+// query is made once per kernel)
+template <typename K>
+int resident_blocks(const Mdp& d, K kern) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> per_cu_of;
+  int per_cu = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = per_cu_of.find((const void*)kern);
+    if (it != per_cu_of.end()) {
+      per_cu = it->second;
+    } else {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = 1;
+      }
+      per_cu_of[(const void*)kern] = per_cu;
+    }
+  }
+  return std::max(1, per_cu) * std::max(1, d.num_cu);
+}
 inline int grid_threads(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kMaxBlocks));
 }
@@ -279,16 +499,28 @@ void by_store(const Mdp& d, F&& f) {
 
 void launch_bellman_dense(Mdp& d, const double* V, double* TV, double* Phi, int32_t* pi,
                           const int32_t* pi_old, double tie_abs, hipStream_t s) {
+  int nb = grid_states(d.n);
   {
     ProfScope p(d, KC_BELLMAN, s);
     by_store(d, [&](auto t) {
       using VT = decltype(t);
-      hipLaunchKernelGGL(k_bellman_dense<VT>, dim3(grid_states(d.n)), dim3(kBlock), 0, s,
-                         (const VT*)d.P, (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi,
-                         pi_old, tie_abs, d.cpi, d.part, vec_ok(d), (const uint8_t*)d.adm);
+      if (vec_ok(d)) {
+        auto go = [&](auto kern) {
+          nb = grid_rounds(d.n, resident_blocks(d, kern));
+          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P,
+                             (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi, pi_old,
+                             tie_abs, d.cpi, d.part, (const uint8_t*)d.adm);
+        };
+        // four rows per group, four loads per row and lane in flight (the
+        // best of 1-4 rows x 4-16 loads measured on c3)
+        go(k_bellman_dense4<VT, 4, 4>);
+      } else
+        hipLaunchKernelGGL(k_bellman_dense<VT>, dim3(grid_states(d.n)), dim3(kBlock), 0, s,
+                           (const VT*)d.P, (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi,
+                           pi, pi_old, tie_abs, d.cpi, d.part, false, (const uint8_t*)d.adm);
     });
   }
-  launch_finalize(d, FIN_BELLMAN, grid_states(d.n), s);
+  launch_finalize(d, FIN_BELLMAN, nb, s);
 }
 
 void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* eta,
@@ -296,14 +528,28 @@ void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, co
   ProfScope p(d, KC_JAPPLY, s);
   by_store(d, [&](auto t) {
     using VT = decltype(t);
-    if (fp32)
-      hipLaunchKernelGGL((k_japply_dense<VT, float, float>), dim3(grid_waves(d.n)), dim3(kBlock),
-                         0, s, (const VT*)d.P, d.m, d.n, (float)d.gamma, pi, (const float*)x, eta,
-                         (float*)y, vec_ok(d));
-    else
-      hipLaunchKernelGGL((k_japply_dense<VT, double, double>), dim3(grid_waves(d.n)),
-                         dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma, pi,
-                         (const double*)x, eta, (double*)y, vec_ok(d));
+    auto go = [&](auto kern, auto xt, int sg) {
+      using X = decltype(xt);
+      const int nb = grid_rounds((d.n + sg - 1) / sg, resident_blocks(d, kern));
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n,
+                         (X)d.gamma, pi, (const X*)x, eta, (X*)y);
+    };
+    // two states per wavefront, four loads per row and lane in flight (the
+    // best of 1-4 states x 2-4 loads measured on c3)
+    if (!vec_ok(d)) {
+      if (fp32)
+        hipLaunchKernelGGL((k_japply_dense<VT, float, float>), dim3(grid_waves(d.n)), dim3(kBlock),
+                           0, s, (const VT*)d.P, d.m, d.n, (float)d.gamma, pi, (const float*)x, eta,
+                           (float*)y, false);
+      else
+        hipLaunchKernelGGL((k_japply_dense<VT, double, double>), dim3(grid_waves(d.n)),
+                           dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma, pi,
+                           (const double*)x, eta, (double*)y, false);
+    } else if (fp32) {
+      go(k_japply_dense_g<VT, float, float, 2, 4>, float{}, 2);
+    } else {
+      go(k_japply_dense_g<VT, double, double, 2, 4>, double{}, 2);
+    }
   });
 }
 
