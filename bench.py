@@ -56,12 +56,25 @@ WORKLOADS = {
 }
 
 
-def kernel_source_hash():
+# sources that define the kernels of a dominant class (plus the shared
+# device helpers): stored counter figures stay valid while these are unchanged
+KERNEL_FILES = {
+    "persistent": ["kernels_persist.hip", "common.hpp"],
+    "sparse": ["kernels_sparse.hip", "common.hpp"],
+    "dense": ["kernels_dense.hip", "common.hpp"],
+}
+
+
+def kernel_source_hash(group):
     h = hashlib.sha256()
-    for f in sorted(os.listdir(KSRC)):
+    for f in KERNEL_FILES[group]:
         with open(os.path.join(KSRC, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
+
+
+def kernel_group(dom, fmt):
+    return "persistent" if dom == "persistent" else ("sparse" if fmt == 0 else "dense")
 
 
 def per_launch_bytes(info, cls, fp32):
@@ -381,7 +394,7 @@ def main():
         tfile = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.workload}.json")
         if os.path.exists(tfile):
             t = json.load(open(tfile))
-            if t.get("kernel_source_hash") == kernel_source_hash():
+            if t.get("kernel_source_hash") == kernel_source_hash(kernel_group(dom, info.fmt)):
                 traffic = t.get("hbm_bytes_per_launch")
         cbw = copy_bandwidth(torch)
         roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
