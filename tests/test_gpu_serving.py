@@ -162,3 +162,54 @@ def test_serving_errors_and_v0():
         V2, pi2, st2 = srv.result(srv.submit(good, params(good), V0=V))
         assert st2["outer"] == 0 and st2["converged"] == 1
         assert np.array_equal(V2, V) and np.array_equal(pi2, pi)
+
+
+def test_serving_action_sets_match_direct_solve():
+    """Requests with state-dependent action sets (excluded rows empty, their
+    costs NaN) are served like any other: bitwise the direct persistent
+    solve with the same workgroup count, and certified on the stored MDP."""
+    I = igm()
+    mdp = synth.with_action_sets(synth.sparse_uniform(9000, 6, 10, 0.95, 41), 0.5, 41)
+    blocks = math.ceil(math.ceil(mdp.n / 64) / BLOCK_SLICES)
+    with I.Server(block_slices=BLOCK_SLICES) as srv:
+        Vs, pis, sts = srv.result(srv.submit(mdp, params(mdp)))
+    with I.mdp_create(mdp, store="fp32") as h:
+        V = zeros(mdp.n)
+        pi = zeros(mdp.n, "int32")
+        h.igmres_pi_solve(V, pi, params(mdp, engine=2, blocks=blocks))
+        Vd, pid = host(V), host(pi)
+    assert np.array_equal(Vs, Vd) and np.array_equal(pis, pid)
+    adm = mdp.adm.reshape(mdp.n, mdp.m)
+    assert adm[np.arange(mdp.n), pis].all()
+    ref = stored_ref(mdp)
+    _, _, res = O.bellman(ref, Vs)
+    assert sts["converged"] == 1 and res <= TOL * (1 + 1e-6)
+
+
+def test_serving_wide_solve_runs_alone():
+    """One CU per XCD stays outside the co-residency budget; a solve asking
+    for more workgroups than the budget holds runs alone and is still exact
+    (the same result as the direct solve with that workgroup count)."""
+    import torch
+    I = igm()
+    num_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    mdp = request_mdp((130000, 6, 12, 0.95, 16))
+    wide = min(256, num_cu)
+    small = [request_mdp(s) for s in MIX[:2]]
+    with I.Server(block_slices=BLOCK_SLICES) as srv:
+        cap = srv.info()["xcd_units_cap"]
+        assert cap == max(1, num_cu // 8 - 1)
+        tickets = [srv.submit(m, params(m)) for m in small]
+        tw = srv.submit(mdp, params(mdp, blocks=wide))
+        tickets += [srv.submit(m, params(m)) for m in small]
+        outs = [srv.result(t) for t in tickets]
+        Vw, piw, stw = srv.result(tw)
+        assert srv.info()["failed"] == 0
+    assert math.ceil(wide / 8) > cap
+    with I.mdp_create(mdp, store="fp32") as h:
+        V = zeros(mdp.n)
+        pi = zeros(mdp.n, "int32")
+        h.igmres_pi_solve(V, pi, params(mdp, engine=2, blocks=wide))
+        assert np.array_equal(Vw, host(V)) and np.array_equal(piw, host(pi))
+    for m, (V, pi, st) in zip(small + small, outs):
+        certify(m, V, pi, st)
