@@ -13,7 +13,7 @@
  * Conventions
  *   - States and actions are 0-based.  Row r = s*m + a of the transition data
  *     holds P(s, a, .); cost[s*m + a] = g(s, a).  Every state has all m
- *     actions.
+ *     actions unless ig_mdp_desc.admissible restricts them (action sets).
  *   - Vectors passed to the solver entry points (V, TV, pi) are DEVICE
  *     pointers owned by the caller (e.g. torch tensors); work is enqueued on
  *     the caller's HIP stream `stream` (hipStream_t passed as void*, NULL =
@@ -166,9 +166,13 @@ void ig_params_default(ig_params* p, double gamma);
  * slice, for CSR input; row-major for dense input) and allocate the solver
  * buffers the solvers share; the Krylov workspace is allocated on the first
  * solve and grown when a later call asks for a longer restart or the FP64
- * basis.  Problem setting: Section 2.  On success *out owns all device
- * memory until mdp_destroy.  Errors: IG_E_INVALID (malformed description,
- * see ig_mdp_desc), IG_E_NOMEM, IG_E_DEVICE. */
+ * basis.  Problem setting: Section 2.  CSR entries are converted on the host
+ * or, for device-resident inputs and from 2^22 entries on, by a device
+ * kernel after one copy of the raw arrays (the environment variable
+ * IG_CONVERT=host|device forces a route); both routes store the same bytes
+ * and report the same first error.  On success *out owns all device memory
+ * until mdp_destroy.  Errors: IG_E_INVALID (malformed description, see
+ * ig_mdp_desc), IG_E_NOMEM, IG_E_DEVICE. */
 ig_status mdp_create(const ig_mdp_desc* desc, void* stream, ig_mdp_t* out);
 
 /* Release the handle and its device memory (synchronises the device).
