@@ -299,7 +299,7 @@ typedef struct {
   size_t arena_bytes, arena_used, arena_peak;
 } ig_server_info;
 
-/* slots 4, prep_threads 2, block_slices 16, max_states 2^19,
+/* slots 4, prep_threads 4, block_slices 16, max_states 2^19,
  * hbm_budget 32 GiB, device 0. */
 void ig_server_config_default(ig_server_config* cfg);
 

@@ -411,7 +411,7 @@ void ig_server_config_default(ig_server_config* cfg) {
   if (!cfg) return;
   cfg->device = 0;
   cfg->slots = 4;
-  cfg->prep_threads = 2;
+  cfg->prep_threads = 4;
   cfg->block_slices = 16;
   cfg->max_states = (int64_t)1 << 19;
   cfg->hbm_budget = (size_t)32 << 30;

@@ -91,7 +91,7 @@ def test_server_config_rejected_before_device_work():
 
 def test_server_config_default():
     c = igm().server_config_default()
-    assert (c.slots, c.prep_threads, c.block_slices, c.max_states) == (4, 2, 16, 1 << 19)
+    assert (c.slots, c.prep_threads, c.block_slices, c.max_states) == (4, 4, 16, 1 << 19)
     assert c.hbm_budget == 32 << 30
 
 
