@@ -128,7 +128,7 @@ def timed_solves(h, fn, V, pi, params, runs, torch):
             "converged": st["converged"]}
 
 
-def comparisons(igmres, torch, mdp, wl, restart, igmres_ms, runs):
+def comparisons(igmres, torch, mdp, wl, restart, igmres_ms, runs, V_main=None):
     """The same workload by the other methods (sparse FP64: exact-evaluation
     PI and OPI with 20 sweeps) or the other precision (mixed workloads: FP64
     storage and arithmetic), each from V0 = 0 to the same tolerance."""
@@ -152,6 +152,12 @@ def comparisons(igmres, torch, mdp, wl, restart, igmres_ms, runs):
             out["fp64"] = timed_solves(h, h.igmres_pi_solve, V, pi, p, runs, torch)
             out["fp64"]["create_ms"] = round(create, 1)
         out["fp64"]["mixed_speedup"] = round(out["fp64"]["ms_p50"] / igmres_ms, 2)
+        if V_main is not None:
+            # the mixed result against the FP64 one: stored-value rounding of P
+            # (reported, not gated) plus both solves' tolerance
+            vf = V.double()
+            out["fp64"]["mixed_rel_diff"] = float((V_main - vf).abs().max() / vf.abs().max())
+            out["fp64"]["fp64_cert_bound"] = float(out["fp64"]["res_inf"] / (1 - mdp.gamma))
     return out
 
 
@@ -166,7 +172,7 @@ def cpu_baseline(mdp, restart, budget_s=12.0):
             O.igmres_pi(mdp, W=restart, tol=1e-8)
             count += 1
             el = time.perf_counter() - t0
-            if el >= budget_s or count >= 200:
+            if el >= budget_s or count >= 1000:
                 break
     return {"value": count / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"{count} full solves of the same workload by the oracle's literal "
@@ -408,7 +414,7 @@ def main():
         print("[bench] comparisons", file=sys.stderr, flush=True)
         runs = 5 if args.workload in ("c1", "c2", "c3") else 2
         try:
-            cmp = comparisons(igmres, torch, mdp, wl, restart, ms_step, runs)
+            cmp = comparisons(igmres, torch, mdp, wl, restart, ms_step, runs, V_main=V.clone())
         except igmres.IgError as e:  # reported, never fatal to the main line
             cmp = {"error": str(e)}
 
