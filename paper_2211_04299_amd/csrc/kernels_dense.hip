@@ -275,10 +275,68 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense4(
   store_partials<4>(v, op, part);
 }
 
-// y = x - gamma P^pi x with one wavefront on SG states at once: their SG
-// rows are streamed together (U 16-byte loads per row and lane in flight)
-// against one load of x per element.  Each row's dot product is
-// accumulated in the order of dense_row_dot.  Rows must be 16-byte aligned.
+// Dot products of SG rows (16-byte aligned, length n) with x * scale, the
+// whole wavefront cooperating, U 16-byte loads per row and lane in flight
+// and one load of x per element for all SG rows.  Each row is accumulated
+// in the order of dense_row_dot; results valid in every lane.
+template <typename VT, typename XT, typename AT, int SG, int U>
+__device__ __forceinline__ void group_dot(const typename Vec<VT>::T* const (&rv)[SG], int64_t n,
+                                          const XT* __restrict__ x, XT scale, int lane,
+                                          AT (&acc)[SG]) {
+  constexpr int N = Vec<VT>::N;
+  using VV = typename Vec<VT>::T;
+  const int64_t nv = n / N;
+#pragma unroll
+  for (int r = 0; r < SG; ++r) acc[r] = 0;
+  int64_t e = lane;
+  for (; e + (U - 1) * kWave < nv; e += U * kWave) {
+    VV p[SG][U];
+#pragma unroll
+    for (int r = 0; r < SG; ++r)
+#pragma unroll
+      for (int u = 0; u < U; ++u) p[r][u] = ldv_nt(rv[r] + e + u * kWave);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      AT xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[u] = (AT)(x[(e + u * kWave) * N + k] * scale);
+#pragma unroll
+      for (int r = 0; r < SG; ++r)
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[r] += (AT)Vec<VT>::at(p[r][u], k) * xv[u];
+    }
+  }
+  for (; e < nv; e += kWave) {
+    VV p[SG];
+#pragma unroll
+    for (int r = 0; r < SG; ++r) p[r] = ldv_nt(rv[r] + e);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const AT xv = (AT)(x[e * N + k] * scale);
+#pragma unroll
+      for (int r = 0; r < SG; ++r) acc[r] += (AT)Vec<VT>::at(p[r], k) * xv;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < SG; ++r) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o);
+  }
+}
+
+// rows (s, pi(s)) of SG consecutive states; past the end, row s0 repeated
+template <typename VT, int SG>
+__device__ __forceinline__ void policy_rows(const VT* __restrict__ P, int m, int64_t n,
+                                            const int32_t* __restrict__ pi, int64_t s0,
+                                            const typename Vec<VT>::T* (&rv)[SG]) {
+#pragma unroll
+  for (int r = 0; r < SG; ++r) {
+    const int64_t s = s0 + r < n ? s0 + r : s0;
+    rv[r] = reinterpret_cast<const typename Vec<VT>::T*>(P + ((int64_t)s * m + pi[s]) * n);
+  }
+}
+
+// y = x - gamma P^pi x with one wavefront on SG states at once (group_dot).
 template <typename VT, typename XT, typename AT, int SG, int U>
 __global__ __launch_bounds__(kBlock) void k_japply_dense_g(const VT* __restrict__ P, int m,
                                                            int64_t n, AT gamma,
@@ -286,58 +344,16 @@ __global__ __launch_bounds__(kBlock) void k_japply_dense_g(const VT* __restrict_
                                                            const XT* __restrict__ x,
                                                            const double* __restrict__ eta,
                                                            XT* __restrict__ y) {
-  constexpr int N = Vec<VT>::N;
-  using VV = typename Vec<VT>::T;
   const int lane = threadIdx.x & (kWave - 1);
   const XT scale = eta ? (XT)(1.0 / *eta) : (XT)1;
-  const int64_t nv = n / N;
   const int64_t ng = (n + SG - 1) / SG;
   for (int64_t gI = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; gI < ng;
        gI += (int64_t)gridDim.x * kWpb) {
     const int64_t s0 = gI * SG;
-    const VV* rv[SG];
-#pragma unroll
-    for (int r = 0; r < SG; ++r) {
-      const int64_t s = s0 + r < n ? s0 + r : s0;  // past the end: repeat row s0, dropped
-      rv[r] = reinterpret_cast<const VV*>(P + ((int64_t)s * m + pi[s]) * n);
-    }
+    const typename Vec<VT>::T* rv[SG];
+    policy_rows<VT, SG>(P, m, n, pi, s0, rv);
     AT acc[SG];
-#pragma unroll
-    for (int r = 0; r < SG; ++r) acc[r] = 0;
-    int64_t e = lane;
-    for (; e + (U - 1) * kWave < nv; e += U * kWave) {
-      VV p[SG][U];
-#pragma unroll
-      for (int r = 0; r < SG; ++r)
-#pragma unroll
-        for (int u = 0; u < U; ++u) p[r][u] = ldv_nt(rv[r] + e + u * kWave);
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        AT xv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = (AT)(x[(e + u * kWave) * N + k] * scale);
-#pragma unroll
-        for (int r = 0; r < SG; ++r)
-#pragma unroll
-          for (int u = 0; u < U; ++u) acc[r] += (AT)Vec<VT>::at(p[r][u], k) * xv[u];
-      }
-    }
-    for (; e < nv; e += kWave) {
-      VV p[SG];
-#pragma unroll
-      for (int r = 0; r < SG; ++r) p[r] = ldv_nt(rv[r] + e);
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const AT xv = (AT)(x[e * N + k] * scale);
-#pragma unroll
-        for (int r = 0; r < SG; ++r) acc[r] += (AT)Vec<VT>::at(p[r], k) * xv;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < SG; ++r) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o);
-    }
+    group_dot<VT, XT, AT, SG, U>(rv, n, x, scale, lane, acc);
     if (lane < SG && s0 + lane < n) {
       AT a = acc[0];
 #pragma unroll
@@ -347,6 +363,47 @@ __global__ __launch_bounds__(kBlock) void k_japply_dense_g(const VT* __restrict_
       y[s] = (XT)((AT)xs - gamma * a);
     }
   }
+}
+
+// The FP64 residual r = g^pi - J V (MODE 0, with ||V||_inf) or the policy
+// sweep T^pi V (MODE 1) on SG states per wavefront (group_dot).
+template <typename VT, int MODE, int SG, int U>
+__global__ __launch_bounds__(kBlock) void k_policy_pass_dense_g(
+    const VT* __restrict__ P, int m, int64_t n, double gamma, const int32_t* __restrict__ pi,
+    const double* __restrict__ cpi, const double* __restrict__ V, double* __restrict__ out,
+    double* __restrict__ part) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double pmax = 0.0, psum = 0.0, vmax = 0.0;
+  const int64_t ng = (n + SG - 1) / SG;
+  for (int64_t gI = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; gI < ng;
+       gI += (int64_t)gridDim.x * kWpb) {
+    const int64_t s0 = gI * SG;
+    const typename Vec<VT>::T* rv[SG];
+    policy_rows<VT, SG>(P, m, n, pi, s0, rv);
+    double acc[SG];
+    group_dot<VT, double, double, SG, U>(rv, n, V, 1.0, lane, acc);
+    if (lane < SG && s0 + lane < n) {
+      double a = acc[0];
+#pragma unroll
+      for (int r = 1; r < SG; ++r) a = lane == r ? acc[r] : a;
+      const int64_t s = s0 + lane;
+      double v;
+      if (MODE == 0) {
+        v = cpi[s] - (V[s] - gamma * a);
+        out[s] = v;
+        vmax = fmax(vmax, fabs(V[s]));
+      } else {
+        const double vn = cpi[s] + gamma * a;
+        v = vn - V[s];
+        out[s] = vn;
+      }
+      pmax = fmax(pmax, fabs(v));
+      psum = fma(v, v, psum);
+    }
+  }
+  double v[3] = {pmax, psum, vmax};
+  const int op[3] = {1, 0, 1};
+  store_partials<3>(v, op, part);
 }
 
 template <typename VT, typename XT, typename AT>
@@ -570,30 +627,46 @@ void launch_pstep_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, con
 }
 
 void launch_residual_dense(Mdp& d, const int32_t* pi, const double* V, double* r, hipStream_t s) {
+  int nb = grid_waves(d.n);
   {
     ProfScope p(d, KC_RESID, s);
     by_store(d, [&](auto t) {
       using VT = decltype(t);
-      hipLaunchKernelGGL((k_policy_pass_dense<VT, 0>), dim3(grid_waves(d.n)), dim3(kBlock), 0, s,
-                         (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, V, r, d.part,
-                         vec_ok(d));
+      if (vec_ok(d)) {
+        auto kern = k_policy_pass_dense_g<VT, 0, 2, 4>;
+        nb = grid_rounds((d.n + 1) / 2, resident_blocks(d, kern));
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma,
+                           pi, (const double*)d.cpi, V, r, d.part);
+      } else {
+        hipLaunchKernelGGL((k_policy_pass_dense<VT, 0>), dim3(nb), dim3(kBlock), 0, s,
+                           (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, V, r,
+                           d.part, false);
+      }
     });
   }
-  launch_finalize(d, FIN_RESID, grid_waves(d.n), s);
+  launch_finalize(d, FIN_RESID, nb, s);
 }
 
 void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double* Vout,
                            hipStream_t s) {
+  int nb = grid_waves(d.n);
   {
     ProfScope p(d, KC_VI, s);
     by_store(d, [&](auto t) {
       using VT = decltype(t);
-      hipLaunchKernelGGL((k_policy_pass_dense<VT, 1>), dim3(grid_waves(d.n)), dim3(kBlock), 0, s,
-                         (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, Vin, Vout,
-                         d.part, vec_ok(d));
+      if (vec_ok(d)) {
+        auto kern = k_policy_pass_dense_g<VT, 1, 2, 4>;
+        nb = grid_rounds((d.n + 1) / 2, resident_blocks(d, kern));
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma,
+                           pi, (const double*)d.cpi, Vin, Vout, d.part);
+      } else {
+        hipLaunchKernelGGL((k_policy_pass_dense<VT, 1>), dim3(nb), dim3(kBlock), 0, s,
+                           (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, Vin, Vout,
+                           d.part, false);
+      }
     });
   }
-  launch_finalize(d, FIN_VI, grid_waves(d.n), s);
+  launch_finalize(d, FIN_VI, nb, s);
 }
 
 void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s) {
