@@ -633,8 +633,8 @@ void launch_residual_dense(Mdp& d, const int32_t* pi, const double* V, double* r
     by_store(d, [&](auto t) {
       using VT = decltype(t);
       if (vec_ok(d)) {
-        auto kern = k_policy_pass_dense_g<VT, 0, 2, 4>;
-        nb = grid_rounds((d.n + 1) / 2, resident_blocks(d, kern));
+        auto kern = k_policy_pass_dense_g<VT, 0, 4, 4>;
+        nb = grid_rounds((d.n + 3) / 4, resident_blocks(d, kern));
         hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma,
                            pi, (const double*)d.cpi, V, r, d.part);
       } else {
@@ -655,8 +655,8 @@ void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double*
     by_store(d, [&](auto t) {
       using VT = decltype(t);
       if (vec_ok(d)) {
-        auto kern = k_policy_pass_dense_g<VT, 1, 2, 4>;
-        nb = grid_rounds((d.n + 1) / 2, resident_blocks(d, kern));
+        auto kern = k_policy_pass_dense_g<VT, 1, 4, 4>;
+        nb = grid_rounds((d.n + 3) / 4, resident_blocks(d, kern));
         hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma,
                            pi, (const double*)d.cpi, Vin, Vout, d.part);
       } else {
