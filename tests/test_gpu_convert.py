@@ -85,32 +85,41 @@ def test_device_route_matches_host_route(name, store, val_type):
     assert_same(a, b)
 
 
-@pytest.mark.parametrize("name", ["uniform", "sets"])
-def test_device_inputs(name):
-    """Arrays already on the device take the device route by default."""
+@pytest.mark.parametrize("name,val_type", [("uniform", "fp64"), ("sets", "fp64"),
+                                           ("uniform", "fp32"), ("sets", "bf16")])
+def test_device_inputs(name, val_type):
+    """Arrays already on the device take the device route by default; the
+    result equals the host route's on the same (rounded) values."""
     import torch
     mdp = case(name)
+    store = "fp64" if val_type == "fp64" else val_type
     with route("host"):
-        a = outputs(mdp, "fp64", "fp64")
+        a = outputs(mdp, store, val_type)
+    vals = synth.round_values(mdp.val, val_type)
     t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).cuda()
+    if val_type == "bf16":
+        dval = torch.from_numpy(vals.view(np.int16).copy()).cuda()
+    else:
+        dval = t(vals, vals.dtype)
     dmdp = synth.MDP(mdp.n, mdp.m, mdp.gamma, t(mdp.cost, np.float64), "csr",
-                     t(mdp.row_ptr, np.int64), t(mdp.col, np.int32), t(mdp.val, np.float64),
+                     t(mdp.row_ptr, np.int64), t(mdp.col, np.int32), dval,
                      None, mdp.name, dict(mdp.meta),
                      None if mdp.adm is None else t(mdp.adm, np.uint8))
     os.environ.pop("IG_CONVERT", None)
-    b = outputs_dev(dmdp)
+    b = outputs_dev(dmdp, store)
     assert_same(a, b)
 
 
-def outputs_dev(dmdp):
+def outputs_dev(dmdp, store):
     I = igm()
     V0 = np.random.default_rng(2).random(dmdp.n) * 10.0
-    with I.mdp_create(dmdp, inputs_on_device=True) as h:
+    mode = "fp64" if store == "fp64" else "mixed"
+    with I.mdp_create(dmdp, store=store, inputs_on_device=True) as h:
         V = dev_vec(V0)
         TV, pi, res = zeros(dmdp.n), zeros(dmdp.n, "int32"), zeros(1)
         h.bellman_apply(V, TV, pi, res)
         Vs, pis = zeros(dmdp.n), zeros(dmdp.n, "int32")
-        st = h.igmres_pi_solve(Vs, pis, I.params_default(dmdp.gamma, tol=1e-8, mode="fp64",
+        st = h.igmres_pi_solve(Vs, pis, I.params_default(dmdp.gamma, tol=1e-8, mode=mode,
                                                          engine=1))
         return host(TV), host(pi), host(res), host(Vs), host(pis), st["outer"], st["inner"]
 
