@@ -166,99 +166,117 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense(
   store_partials<4>(v, op, part);
 }
 
-// Bellman pass with one wavefront per state: its action rows are streamed
-// RG at a time, U 16-byte loads per row and lane in flight, against one
-// load of V per element and group.  Each row's dot product is accumulated
-// in the same order as dense_row_dot, and the actions are visited in
+// Bellman pass with one wavefront on SGB states at once: their action rows
+// are streamed RG actions at a time (SGB * RG rows, U 16-byte loads per row
+// and lane in flight) against a single load of V per element, which every
+// row of the group shares.  Each row's dot product is accumulated in the
+// same order as dense_row_dot, and each state's actions are visited in
 // increasing order (lowest index wins ties), as in k_bellman_dense.  Rows
 // must be 16-byte aligned (vec_ok).
-template <typename VT, int RG, int U>
+template <typename VT, int SGB, int RG, int U>
 __global__ __launch_bounds__(kBlock) void k_bellman_dense4(
     const VT* __restrict__ P, const double* __restrict__ cost, int m, int64_t n, double gamma,
     const double* __restrict__ V, double* __restrict__ TV, double* __restrict__ Phi,
     int32_t* __restrict__ pi, const int32_t* __restrict__ pi_old, double tie_abs,
     double* __restrict__ cpi, double* __restrict__ part, const uint8_t* __restrict__ adm) {
   constexpr int N = Vec<VT>::N;
+  constexpr int R = SGB * RG;  // rows in flight: row q is action a0 + q % RG of state s0 + q / RG
   using VV = typename Vec<VT>::T;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t nv = n / N;
+  const int64_t ng = (n + SGB - 1) / SGB;
   double pmax = 0.0, psum = 0.0, nonfin = 0.0, chg = 0.0;
-  for (int64_t s = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; s < n;
-       s += (int64_t)gridDim.x * kWpb) {
-    const int inc = pi_old ? pi_old[s] : -1;
-    double best = INFINITY, qinc = INFINITY;
-    int besta = m;
+  for (int64_t gI = (int64_t)blockIdx.x * kWpb + threadIdx.x / kWave; gI < ng;
+       gI += (int64_t)gridDim.x * kWpb) {
+    const int64_t s0 = gI * SGB;
+    int inc[SGB], besta[SGB];
+    double best[SGB], qinc[SGB];
+#pragma unroll
+    for (int j = 0; j < SGB; ++j) {
+      const int64_t s = s0 + j < n ? s0 + j : s0;
+      inc[j] = pi_old ? pi_old[s] : -1;
+      best[j] = INFINITY;
+      qinc[j] = INFINITY;
+      besta[j] = m;
+    }
     for (int a0 = 0; a0 < m; a0 += RG) {
-      bool use[RG];
-      const VV* rv[RG];
+      bool use[R];
+      const VV* rv[R];
 #pragma unroll
-      for (int r = 0; r < RG; ++r) {
-        const int a = a0 + r;
-        use[r] = a < m && (!adm || adm[(int64_t)a * n + s]);
-        // an unused slot re-reads row a0 (in cache) and is dropped
-        rv[r] = reinterpret_cast<const VV*>(P + ((int64_t)s * m + (a < m ? a : a0)) * n);
+      for (int q = 0; q < R; ++q) {
+        const int j = q / RG, a = a0 + q % RG;
+        const bool sv = s0 + j < n;
+        const int64_t s = sv ? s0 + j : s0;
+        use[q] = sv && a < m && (!adm || adm[(int64_t)a * n + s]);
+        // an unused slot re-reads row (s, a0) (in cache) and is dropped
+        rv[q] = reinterpret_cast<const VV*>(P + ((int64_t)s * m + (a < m ? a : a0)) * n);
       }
-      double acc[RG];
+      double acc[R];
 #pragma unroll
-      for (int r = 0; r < RG; ++r) acc[r] = 0.0;
+      for (int q = 0; q < R; ++q) acc[q] = 0.0;
       int64_t e = lane;
       for (; e + (U - 1) * kWave < nv; e += U * kWave) {
-        VV p[RG][U];
+        VV p[R][U];
 #pragma unroll
-        for (int r = 0; r < RG; ++r)
+        for (int q = 0; q < R; ++q)
 #pragma unroll
-          for (int u = 0; u < U; ++u) p[r][u] = ldv_nt(rv[r] + e + u * kWave);
+          for (int u = 0; u < U; ++u) p[q][u] = ldv_nt(rv[q] + e + u * kWave);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
           double x[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) x[u] = V[(e + u * kWave) * N + k];
 #pragma unroll
-          for (int r = 0; r < RG; ++r)
+          for (int q = 0; q < R; ++q)
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc[r] += Vec<VT>::at(p[r][u], k) * x[u];
+            for (int u = 0; u < U; ++u) acc[q] += Vec<VT>::at(p[q][u], k) * x[u];
         }
       }
       for (; e < nv; e += kWave) {
-        VV p[RG];
+        VV p[R];
 #pragma unroll
-        for (int r = 0; r < RG; ++r) p[r] = ldv_nt(rv[r] + e);
+        for (int q = 0; q < R; ++q) p[q] = ldv_nt(rv[q] + e);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
           const double x0 = V[e * N + k];
 #pragma unroll
-          for (int r = 0; r < RG; ++r) acc[r] += Vec<VT>::at(p[r], k) * x0;
+          for (int q = 0; q < R; ++q) acc[q] += Vec<VT>::at(p[q], k) * x0;
         }
       }
 #pragma unroll
-      for (int r = 0; r < RG; ++r) {
+      for (int q = 0; q < R; ++q) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o);
+        for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
       }
 #pragma unroll
-      for (int r = 0; r < RG; ++r) {
-        if (!use[r]) continue;
-        const int a = a0 + r;
-        const double q = cost[(int64_t)a * n + s] + gamma * acc[r];
-        if (!(q - q == 0.0)) nonfin += lane == 0 ? 1.0 : 0.0;
-        if (q < best) {
-          best = q;
-          besta = a;
+      for (int q = 0; q < R; ++q) {
+        if (!use[q]) continue;
+        const int j = q / RG, a = a0 + q % RG;
+        const double qv = cost[(int64_t)a * n + s0 + j] + gamma * acc[q];
+        if (!(qv - qv == 0.0)) nonfin += lane == 0 ? 1.0 : 0.0;
+        if (qv < best[j]) {
+          best[j] = qv;
+          besta[j] = a;
         }
-        if (a == inc) qinc = q;
+        if (a == inc[j]) qinc[j] = qv;
       }
     }
-    if (besta >= m) {
-      besta = 0;
-      best = NAN;
-    }
-    int astar = besta;
-    double tv = best;
-    if (inc >= 0 && inc < m && qinc <= best + tie_abs) {
-      astar = inc;
-      tv = qinc;
-    }
-    if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < SGB; ++j) {
+      const int64_t s = s0 + j;
+      if (lane != 0 || s >= n) continue;
+      int bj = besta[j];
+      double bv = best[j];
+      if (bj >= m) {
+        bj = 0;
+        bv = NAN;
+      }
+      int astar = bj;
+      double tv = bv;
+      if (inc[j] >= 0 && inc[j] < m && qinc[j] <= bv + tie_abs) {
+        astar = inc[j];
+        tv = qinc[j];
+      }
       const double phi = tv - V[s];
       if (TV) TV[s] = tv;
       Phi[s] = phi;
@@ -267,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_bellman_dense4(
       if (!(phi - phi == 0.0)) nonfin += 1.0;  // NaN/Inf in V itself
       pmax = fmax(pmax, fabs(phi));
       psum = fma(phi, phi, psum);
-      if (pi_old && astar != inc) chg += 1.0;
+      if (pi_old && astar != inc[j]) chg += 1.0;
     }
   }
   double v[4] = {pmax, psum, nonfin, chg};
@@ -562,15 +580,16 @@ void launch_bellman_dense(Mdp& d, const double* V, double* TV, double* Phi, int3
     by_store(d, [&](auto t) {
       using VT = decltype(t);
       if (vec_ok(d)) {
-        auto go = [&](auto kern) {
-          nb = grid_rounds(d.n, resident_blocks(d, kern));
+        auto go = [&](auto kern, int sgb) {
+          nb = grid_rounds((d.n + sgb - 1) / sgb, resident_blocks(d, kern));
           hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P,
                              (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi, pi_old,
                              tie_abs, d.cpi, d.part, (const uint8_t*)d.adm);
         };
-        // four rows per group, four loads per row and lane in flight (the
-        // best of 1-4 rows x 4-16 loads measured on c3)
-        go(k_bellman_dense4<VT, 4, 4>);
+        // two states, four actions each, two loads per row and lane in
+        // flight (the best of 1-8 states x 1-4 actions x 1-4 loads measured
+        // on c3: 264 against 322 us for one state x four actions x four loads)
+        go(k_bellman_dense4<VT, 2, 4, 2>, 2);
       } else
         hipLaunchKernelGGL(k_bellman_dense<VT>, dim3(grid_states(d.n)), dim3(kBlock), 0, s,
                            (const VT*)d.P, (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi,
