@@ -145,7 +145,8 @@ void launch_japply_sparse(Mdp& d, bool fp32, const void* x, const double* eta, v
 // r = g^pi - (V - gamma P^pi V) in FP64, with max|r| and ||r||^2 into status.
 void launch_residual_sparse(Mdp& d, const double* V, double* r, hipStream_t s);
 // Vout = g^pi + gamma P^pi Vin (FP64), max|Vout - Vin| into status.aux.
-void launch_vi_sweep_sparse(Mdp& d, const double* Vin, double* Vout, hipStream_t s);
+void launch_vi_sweep_sparse(Mdp& d, const double* Vin, double* Vout, hipStream_t s,
+                            bool finish = true);
 // compact P^pi and g^pi for a given policy; #invalid entries into status.changes
 void launch_gather_policy_sparse(Mdp& d, const int32_t* pi, hipStream_t s);
 
@@ -156,7 +157,7 @@ void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, co
                          void* y, hipStream_t s);
 void launch_residual_dense(Mdp& d, const int32_t* pi, const double* V, double* r, hipStream_t s);
 void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double* Vout,
-                           hipStream_t s);
+                           hipStream_t s, bool finish = true);
 void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s);
 
 // ---- persistent single-launch solver (sparse, up to kPMaxBlocks*kPMaxSpb slices)

@@ -667,7 +667,7 @@ void launch_residual_dense(Mdp& d, const int32_t* pi, const double* V, double* r
 }
 
 void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double* Vout,
-                           hipStream_t s) {
+                           hipStream_t s, bool finish) {
   int nb = grid_waves(d.n);
   {
     ProfScope p(d, KC_VI, s);
@@ -685,7 +685,7 @@ void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double*
       }
     });
   }
-  launch_finalize(d, FIN_VI, nb, s);
+  if (finish) launch_finalize(d, FIN_VI, nb, s);
 }
 
 void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s) {

@@ -408,12 +408,12 @@ void launch_residual_sparse(Mdp& d, const double* V, double* r, hipStream_t s) {
   launch_finalize(d, FIN_RESID, grid_for(d, d.G_jap), s);
 }
 
-void launch_vi_sweep_sparse(Mdp& d, const double* Vin, double* Vout, hipStream_t s) {
+void launch_vi_sweep_sparse(Mdp& d, const double* Vin, double* Vout, hipStream_t s, bool finish) {
   {
     ProfScope p(d, KC_VI, s);
     dispatch_vt_g<RunVi>(d, d.G_jap, d, Vin, Vout, s);
   }
-  launch_finalize(d, FIN_VI, grid_for(d, d.G_jap), s);
+  if (finish) launch_finalize(d, FIN_VI, grid_for(d, d.G_jap), s);
 }
 
 void launch_gather_policy_sparse(Mdp& d, const int32_t* pi, hipStream_t s) {

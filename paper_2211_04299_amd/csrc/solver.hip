@@ -45,11 +45,14 @@ void k_residual(Mdp& d, const int32_t* pi, const double* V, double* r, hipStream
   else
     launch_residual_dense(d, pi, V, r, s);
 }
-void k_vi(Mdp& d, const int32_t* pi, const double* Vin, double* Vout, hipStream_t s) {
+// one application of T^pi; `finish` reduces its difference norms (not
+// needed by OPI's fixed sweeps)
+void k_vi(Mdp& d, const int32_t* pi, const double* Vin, double* Vout, hipStream_t s,
+          bool finish = true) {
   if (d.fmt == IG_FMT_CSR)
-    launch_vi_sweep_sparse(d, Vin, Vout, s);
+    launch_vi_sweep_sparse(d, Vin, Vout, s, finish);
   else
-    launch_vi_sweep_dense(d, pi, Vin, Vout, s);
+    launch_vi_sweep_dense(d, pi, Vin, Vout, s, finish);
 }
 void k_gather(Mdp& d, const int32_t* pi, hipStream_t s) {
   if (d.fmt == IG_FMT_CSR)
@@ -351,7 +354,7 @@ ig_status run_opi(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& 
     double* cur = d.ws.t;
     double* other = V;
     for (int j = 1; j < p.opi_sweeps; ++j) {
-      k_vi(d, pi, cur, other, s);
+      k_vi(d, pi, cur, other, s, false);
       st.alg_bytes += B.vi();
       std::swap(cur, other);
     }
