@@ -115,6 +115,19 @@ ig_status dmalloc(T** p, size_t bytes) {
   return IG_OK;
 }
 
+// A temporary allocation from the top of the handle's region (region mode):
+// `used` does not move, so the allocations made after the create has
+// synchronised may reuse these bytes.  *top counts the bytes taken so far.
+template <typename T>
+ig_status dmalloc_top(T** p, size_t bytes, size_t* top) {
+  const size_t b = round256(bytes);
+  if (t_region->used + *top + b > t_region->size)
+    return fail(IG_E_TOO_LARGE, "device region too small for the MDP");
+  *top += b;
+  *p = (T*)(t_region->base + t_region->size - *top);
+  return IG_OK;
+}
+
 // host -> device copy; in region mode asynchronous on the handle's stream
 // (the caller keeps `src` alive until the stream has passed the copy)
 ig_status upload(Mdp* d, void* dst, const void* src, size_t bytes) {
@@ -617,6 +630,7 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       char* val_d = nullptr;
       unsigned long long* err_d = nullptr;
       const bool temp = d->region == nullptr;  // plain allocations to free here
+      size_t top = 0;                           // region mode: bytes taken from its top
       auto free_temp = [&]() {
         if (!temp) return;
         if (!ondev) {
@@ -630,12 +644,16 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         rp_d = const_cast<int64_t*>(desc->row_ptr);
         col_d = const_cast<int32_t*>(desc->col);
         val_d = (char*)const_cast<void*>(desc->val);
-      } else if (dmalloc(&rp_d, ((size_t)R + 1) * 8) || dmalloc(&col_d, (size_t)nnz * 4) ||
-                 dmalloc(&val_d, (size_t)nnz * vin)) {
+      } else if (temp ? (dmalloc(&rp_d, ((size_t)R + 1) * 8) || dmalloc(&col_d, (size_t)nnz * 4) ||
+                         dmalloc(&val_d, (size_t)nnz * vin))
+                      : (dmalloc_top(&rp_d, ((size_t)R + 1) * 8, &top) ||
+                         dmalloc_top(&col_d, (size_t)nnz * 4, &top) ||
+                         dmalloc_top(&val_d, (size_t)nnz * vin, &top))) {
         free_temp();
         return fail(IG_E_NOMEM, "device staging of the CSR arrays");
       }
-      if (dmalloc(&err_d, 5 * sizeof(unsigned long long))) {
+      if (temp ? dmalloc(&err_d, 5 * sizeof(unsigned long long))
+               : dmalloc_top(&err_d, 5 * sizeof(unsigned long long), &top)) {
         free_temp();
         return fail(IG_E_NOMEM, "device staging of the CSR arrays");
       }
@@ -843,7 +861,7 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
   if (!desc || !bytes || desc->n < 1 || desc->m < 1) return fail(IG_E_INVALID, "bad description");
   const int64_t n = desc->n, R = n * (int64_t)desc->m;
   const size_t vb = dtype_bytes(desc->store);
-  size_t b = 0;
+  size_t b = 0, staging = 0;
   if (desc->fmt == IG_FMT_CSR) {
     if (desc->inputs_on_device) return fail(IG_E_INVALID, "footprint needs host CSR arrays");
     const int64_t* rp = desc->row_ptr;
@@ -866,20 +884,23 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
     }
     b += round256(tot * 4) + round256(tot * vb) + 2 * round256(ns * 8) + 2 * round256(ns * 4) +
          round256(totp * 4) + round256(totp * vb);
-    // raw CSR staging of the device conversion (region handles use it)
+    // raw CSR staging of the device conversion: taken from the top of a
+    // region after the sliced-ELL arrays (and the mask), dead once the
+    // conversion is done, so the later allocations may reuse its bytes
     const int64_t nnz = rp[R];
-    b += round256((R + 1) * 8) + round256(nnz * 4) + round256(nnz * dtype_bytes(desc->val_type)) +
-         round256(5 * sizeof(unsigned long long));
+    staging = round256((R + 1) * 8) + round256(nnz * 4) + round256(nnz * dtype_bytes(desc->val_type)) +
+              round256(5 * sizeof(unsigned long long));
   } else {
     b += round256((size_t)R * n * vb);
   }
   if (desc->admissible) b += round256(R);
+  const size_t at_staging = b + staging;
   b += round256(R * 8) + round256(n * 8) + round256(sizeof(DevStatus)) +
        round256(sizeof(GivensState)) + round256(part_doubles(n) * 8) + round256(sizeof(PCtl));
   const size_t xb = fp32 ? 4 : 8;
   b += 3 * round256(n * 8) + round256(n * 4);                             // Vb, r, t, pi
   b += round256((size_t)(restart + 1) * n * xb) + 2 * round256(n * xb);  // Q, wA, wB
-  *bytes = b;
+  *bytes = std::max(b, at_staging);
   return IG_OK;
 }
 
