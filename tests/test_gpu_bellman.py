@@ -105,3 +105,16 @@ def test_bellman_nan_reported():
         with pytest.raises(I.IgError) as e:
             h.igmres_pi_solve(Vd, pi, p)
         assert e.value.status == I.IG_E_NUMERIC
+
+
+@pytest.mark.parametrize("m,store,sets", [(5, "fp32", False), (6, "bf16", False), (5, "fp32", True),
+                                          (7, "fp64", True)])
+def test_bellman_dense_action_groups(m, store, sets):
+    """Dense rows streamed several states and four actions at a time: action
+    counts that are not a multiple of four, excluded actions inside a
+    group, and group tails (n not a multiple of the states per group)."""
+    n = 208 if store == "bf16" else 204
+    mdp = synth.dense_exp(n, m, 0.97, seed=11 + m)
+    if sets:
+        mdp = synth.with_action_sets(mdp, 0.5, 12 + m)
+    check(mdp, np.random.default_rng(m).normal(size=n) * 5, store=store)
