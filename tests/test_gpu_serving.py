@@ -213,3 +213,25 @@ def test_serving_wide_solve_runs_alone():
         assert np.array_equal(Vw, host(V)) and np.array_equal(piw, host(pi))
     for m, (V, pi, st) in zip(small + small, outs):
         certify(m, V, pi, st)
+
+
+def test_serving_storage_and_modes_mix():
+    """Requests with different storage types and arithmetic modes share one
+    server; each equals the direct persistent solve of the same handle
+    configuration bit for bit."""
+    I = igm()
+    mdp = request_mdp((6000, 5, 10, 0.95, 51))
+    blocks = math.ceil(math.ceil(mdp.n / 64) / BLOCK_SLICES)
+    combos = [("fp64", "fp64"), ("fp64", "mixed"), ("fp32", "mixed"), ("bf16", "mixed")]
+    with I.Server(block_slices=BLOCK_SLICES) as srv:
+        tickets = [srv.submit(mdp, params(mdp, mode=mode), store=store) for store, mode in combos]
+        served = [srv.result(t) for t in tickets]
+        assert srv.info()["failed"] == 0
+    for (store, mode), (Vs, pis, sts) in zip(combos, served):
+        with I.mdp_create(mdp, store=store) as h:
+            V = zeros(mdp.n)
+            pi = zeros(mdp.n, "int32")
+            h.igmres_pi_solve(V, pi, params(mdp, mode=mode, engine=2, blocks=blocks))
+            assert np.array_equal(Vs, host(V)), (store, mode)
+            assert np.array_equal(pis, host(pi)), (store, mode)
+        assert sts["converged"] == 1
