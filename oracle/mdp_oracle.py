@@ -35,6 +35,13 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
                            (eq. 13) computed from an explicitly formed Krylov
                            matrix, by agreement with LU at alpha -> 0, and by
                            agreement of the returned V with PI-LU's V*.
+                           Option forcing: alpha_k = min(alpha,
+                           ||T V_k - V_k||_inf^(1/2)), a forcing sequence that
+                           tends to zero (Theorem 1's superlinear case).
+                           Pinned by identity with the constant-alpha run while
+                           alpha_k = alpha, by the inexactness condition of
+                           eq. 11 at every outer step, by residual ratios that
+                           tend to zero, and by PI-LU's V*.
   neumann_apply            M^{-1} = sum_{k<=d} (gamma P^pi)^k, the truncated
                            series of Lemma 3's proof, as a right
                            preconditioner of the inner GMRES (future work
@@ -275,6 +282,7 @@ class OracleStats:
     breakdowns: int = 0
     inner_per_outer: list = field(default_factory=list)
     res_history: list = field(default_factory=list)
+    alpha_history: list = field(default_factory=list)  # inner tolerance factor per outer step
     converged: bool = False
 
 
@@ -377,12 +385,15 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
 
 
 def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inner=10_000,
-              precond=0):
+              precond=0, forcing=False):
     """Algorithm 2 with outer termination at ||T V_k - V_k||_inf <= tol.
 
     alpha defaults to the midpoint of Theorem 1's admissible range,
-    0.5 * (1 - gamma) / (1 + gamma).  Returns (V, pi, OracleStats); V and pi
-    are V_k and GreedyPolicy(V_k) of the terminating outer step.
+    0.5 * (1 - gamma) / (1 + gamma).  forcing: the inner tolerance of outer
+    step k uses alpha_k = min(alpha, ||T V_k - V_k||_inf^(1/2)), a forcing
+    sequence tending to zero (the superlinear case of Theorem 1) instead of
+    the constant alpha.  Returns (V, pi, OracleStats); V and pi are V_k and
+    GreedyPolicy(V_k) of the terminating outer step.
     """
     g = mdp.gamma
     if alpha is None:
@@ -397,7 +408,9 @@ def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inne
             st.outer = k
             return V, pi, st
         Phi = policy_cost(mdp, pi) - j_apply(mdp, pi, V)
-        V, info = gmres_inner(mdp, pi, V, alpha, W, max_inner,
+        alpha_k = min(alpha, float(np.sqrt(res))) if forcing else alpha
+        st.alpha_history.append(alpha_k)
+        V, info = gmres_inner(mdp, pi, V, alpha_k, W, max_inner,
                               ref_inf=float(np.max(np.abs(Phi))), precond=precond)
         st.inner += info["steps"]
         st.restarts += info["restarts"]

@@ -79,6 +79,32 @@ def test_igmres_c2_parity_tight(engine):
     assert_policy_match(mdp, Vs, pis, pi)
 
 
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("name,seed,W", [("c1", 0, 20), ("c1", 1, 20), ("c2", 0, 30)])
+def test_igmres_forcing_parity(name, seed, W, engine):
+    """forcing=1: alpha_k = min(alpha, sqrt(||T V_k - V_k||_inf)), Theorem 1's
+    superlinear case; same V*, policy and outer steps as the oracle's run
+    with the same forcing sequence, and no more outer steps than alpha_k = alpha."""
+    mdp, Vs, pis = reference(name, seed)
+    tol = tol_par(mdp, np.max(np.abs(Vs)))
+    V, pi, st = solve(mdp, tol=tol, restart=W, engine=engine, forcing=1)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+    Vo, pio, sto = O.igmres_pi(mdp, W=W, tol=tol, forcing=True)
+    assert st["outer"] == sto.outer
+    assert abs(st["inner"] - sto.inner) <= sto.outer
+    _, _, st0 = solve(mdp, tol=tol, restart=W, engine=engine)
+    assert st["outer"] <= st0["outer"]
+
+
+def test_ipi_vi_forcing_c1():
+    mdp, Vs, pis = reference("c1", 1)
+    V, pi, st = solve(mdp, method="ipi_vi_solve", tol=1e-10, forcing=1)
+    assert st["converged"] == 1
+    assert np.max(np.abs(V - Vs)) <= 1e-10 / (1 - mdp.gamma) * (1 + 1e-6)
+
 def test_pi_solve_c2():
     mdp, Vs, pis = reference("c2", 0)
     V, pi, st = solve(mdp, method="pi_solve", restart=30)

@@ -431,3 +431,64 @@ def test_preconditioned_igmres_reaches_optimum_in_fewer_steps(d):
     assert np.array_equal(pi[sel], pis[sel])
     # each preconditioned step covers d+1 products: fewer Arnoldi steps
     assert st.inner < st0.inner
+
+
+# --- forcing sequence alpha_k = min(alpha, ||T V_k - V_k||_inf^(1/2)) (Theorem 1) ---
+
+def test_forcing_equals_constant_alpha_while_alpha_is_smaller():
+    """While sqrt(||T V_k - V_k||) >= alpha at every outer step, alpha_k is alpha
+    and the forcing run is Algorithm 2 itself, bit for bit."""
+    mdp = synth.config("c1", 0)
+    alpha = 0.5 * (1 - mdp.gamma) / (1 + mdp.gamma)
+    tol = 1e-3  # every residual seen before stopping stays above alpha^2 ~ 6.9e-4
+    Va, pia, sta = O.igmres_pi(mdp, W=20, tol=tol)
+    Vb, pib, stb = O.igmres_pi(mdp, W=20, tol=tol, forcing=True)
+    assert sta.outer >= 3
+    assert min(sta.res_history[:-1]) >= alpha ** 2
+    assert np.array_equal(Va, Vb) and np.array_equal(pia, pib)
+    assert sta.inner == stb.inner and sta.res_history == stb.res_history
+
+
+def test_forcing_inexactness_condition_each_outer_step():
+    """Each outer step's inner solve ends with ||g^pi - J^pi V_{k+1}||_inf <=
+    alpha_k ||T V_k - V_k||_inf (eq. 11 with alpha_k), and alpha_k falls below
+    the constant alpha once the residual is small; replayed step by step with
+    max_outer, the runs are prefixes of each other."""
+    mdp = synth.sparse_uniform(400, 4, 6, 0.99, seed=21)
+    alpha = 0.5 * (1 - mdp.gamma) / (1 + mdp.gamma)
+    V, pi, st = O.igmres_pi(mdp, W=15, tol=1e-11, forcing=True)
+    assert st.converged
+    Vk = np.zeros(mdp.n)
+    for k in range(st.outer):
+        _, pik, res = O.bellman(mdp, Vk)
+        Vn, _, stk = O.igmres_pi(mdp, W=15, tol=0.0, max_outer=k + 1, forcing=True)
+        r = np.max(np.abs(O.policy_cost(mdp, pik) - O.j_apply(mdp, pik, Vn)))
+        ak = st.alpha_history[k]
+        assert ak <= alpha and ak > 0.0
+        assert r <= ak * res * (1 + 1e-12)
+        Vk = Vn
+    assert min(st.alpha_history) < alpha / 10
+    np.testing.assert_array_equal(Vk, V)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_forcing_superlinear_and_optimal(seed):
+    """Theorem 1: with alpha_k -> 0 the residual ratio ||T V_{k+1} - V_{k+1}|| /
+    ||T V_k - V_k|| tends to zero, while the constant-alpha run contracts at a
+    steady rate; both end at PI-LU's V* with an optimal policy."""
+    mdp = synth.config("c1", seed)
+    Vs, pis, _ = O.policy_iteration(mdp)
+    tol = 1e-11 * np.max(np.abs(Vs))
+    V, pi, st = O.igmres_pi(mdp, W=20, tol=tol, forcing=True)
+    V0, _, st0 = O.igmres_pi(mdp, W=20, tol=tol)
+    assert st.converged and st0.converged
+    assert np.max(np.abs(V - Vs)) <= 1e-9 * np.max(np.abs(Vs))
+    sel = O.action_gaps(mdp, Vs) > 1e-9
+    assert np.array_equal(pi[sel], pis[sel])
+    rf = np.asarray(st.res_history)
+    r0 = np.asarray(st0.res_history)
+    ratios_f = rf[-3:] / rf[-4:-1]
+    ratios_0 = r0[-3:] / r0[-4:-1]
+    assert ratios_f[-1] < ratios_f[0] and ratios_f[-1] < 1e-3
+    assert np.min(ratios_0) > 10 * ratios_f[-1]
+    assert st.outer <= st0.outer
