@@ -26,7 +26,9 @@
 // When the residual bracket ||r||_inf <= rho <= sqrt(n) ||r||_inf cannot
 // decide the stopping test, the iterate is formed and the true FP64 residual
 // evaluated (two more barriers).
+#include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -65,6 +67,7 @@ struct PArgs {
   PCtl* __restrict__ ctl;
   double alpha, tol, sqrt_n;
   int W, max_outer, max_inner, forcing;
+  int vlds;  // the Bellman pass gathers V from a copy in LDS (n doubles fit)
   double b_bellman, b_japply, b_vec, b_resid;  // algorithmic bytes per event
 };
 
@@ -95,29 +98,40 @@ __device__ __forceinline__ unsigned ld_flag(const unsigned* p) {
 }
 
 // Grid barrier on per-block arrival words.  Returns false (uniformly in the
-// block) if any wait exceeded the spin limit.
-__device__ __forceinline__ bool gbarrier(unsigned int* flags, PCtl* ctl, unsigned epoch) {
-  __shared__ int s_ok;
+// block) if a wait exceeded the spin limit or, while this block waited,
+// another block had already failed its own wait: a block that fails leaves
+// without arriving at the next barrier, so every other block either finds the
+// error flag during that wait or times out itself, and the grid drains.  A
+// barrier whose arrivals are all seen completes without reading the flag.
+// bad: two LDS words, zero at launch, used by barrier parity; each barrier
+// clears the word of the next one (all threads read it before this barrier).
+__device__ __forceinline__ bool gbarrier(unsigned int* flags, PCtl* ctl, unsigned epoch,
+                                         int* bad) {
   __syncthreads();
   if (gridDim.x == 1) return true;  // one block: the block barrier orders everything
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
+    bad[(epoch + 1) & 1] = 0;
     __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (threadIdx.x < gridDim.x) {
     long spins = 0;
     while (ld_flag(&flags[threadIdx.x]) < epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) {
         __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bad[epoch & 1] = 1;
+        break;
+      }
+      if ((spins & 1023) == 0 &&
+          __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        bad[epoch & 1] = 1;
         break;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  if (threadIdx.x == 0)
-    s_ok = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-  __syncthreads();
-  return s_ok != 0;
+  return bad[epoch & 1] == 0;
 }
 
 // out[c] = sum (or max: maxmask bit c, or c == maxcol) over blocks of
@@ -390,9 +404,12 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
   __shared__ double psum[kPB];
   __shared__ double psum2[kPB];
 
+  __shared__ int s_bad[2];  // barrier failure words, by barrier parity
+
   if (threadIdx.x == 0) {
     sc = Scal{};
     sc.dec = D_NEXT;
+    s_bad[0] = s_bad[1] = 0;
   }
   __syncthreads();
   unsigned epoch = 0;
@@ -410,7 +427,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
     __syncthreads();
     own_axpy<XT>(Qv, nown, cols, coef, 1.0, psum, [&](int t) { return A.Vb[s_lo + t]; },
                  [&](int t, double v) { A.V[s_lo + t] = v; });
-    if (!gbarrier(A.flags, A.ctl, ++epoch)) return false;
+    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad)) return false;
     {
       double pmax = 0.0, ps = 0.0;
       for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
@@ -429,7 +446,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
       const int op[2] = {1, 0};
       block_reduce_big<2>(v, op, MYPART);
     }
-    if (!gbarrier(A.flags, A.ctl, ++epoch)) return false;
+    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad)) return false;
     reduce_rows(PARTS, 2, 1u, red);
     if (threadIdx.x == 0) {
       sc.alg_bytes += A.b_resid + A.b_vec * (cols + 2.0);
@@ -443,69 +460,81 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
 
 #define IG_BARRIER()                                    \
   do {                                                  \
-    if (!gbarrier(A.flags, A.ctl, ++epoch)) goto leave; \
+    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad)) goto leave; \
   } while (0)
 
   for (int k = 0;; ++k) {
     // ---------------- Bellman pass: pi_k, Phi_k = T V_k - V_k, g^pi, P^pi
     {
       double pmax = 0.0, psum = 0.0, nonfin = 0.0;
-      for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
-        const int64_t s = base + ls;
-        const bool valid = s < n;
-        const int64_t sc2 = valid ? s : n - 1;
-        const int64_t b = s >> 6;
-        const int l = (int)(s & 63);
-        const int Kb = A.P.width[b], Mb = A.P.mcnt[b];
-        const int64_t ob = A.P.off[b];
-        double best = INFINITY;
-        int besta = A.m;
-        auto candidate = [&](int a, double q) {
-          if (A.P.adm && !A.P.adm[(int64_t)a * n + sc2]) return;  // a is not in A(s)
-          if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;
-          if (q < best) {  // increasing a: lowest index wins ties
-            best = q;
-            besta = a;
+      // The V gathers (m*k per state) read a copy of V in LDS when it fits: the
+      // basis and product rows there are dead between inner solves.
+      auto rows = [&](auto in_lds) {
+        const double* __restrict__ Vg = decltype(in_lds)::value ? dsm : A.V;
+        for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
+          const int64_t s = base + ls;
+          const bool valid = s < n;
+          const int64_t sc2 = valid ? s : n - 1;
+          const int64_t b = s >> 6;
+          const int l = (int)(s & 63);
+          const int Kb = A.P.width[b], Mb = A.P.mcnt[b];
+          const int64_t ob = A.P.off[b];
+          double best = INFINITY;
+          int besta = A.m;
+          auto candidate = [&](int a, double q) {
+            if (A.P.adm && !A.P.adm[(int64_t)a * n + sc2]) return;  // a is not in A(s)
+            if (!(q - q == 0.0)) nonfin += valid ? 1.0 : 0.0;
+            if (q < best) {  // increasing a: lowest index wins ties
+              best = q;
+              besta = a;
+            }
+          };
+          for (int a = g; a < Mb; a += G) {
+            const int64_t bs = ob + (((int64_t)a * Kb) << 6) + l;
+            double acc = 0.0;
+  #pragma unroll 8
+            for (int j = 0; j < Kb; ++j) {
+              const int64_t e = bs + ((int64_t)j << 6);
+              acc = fma(to_d(A.P.val[e]), Vg[A.P.col[e]], acc);
+            }
+            candidate(a, A.cost[(int64_t)a * n + sc2] + A.gamma * acc);
           }
-        };
-        for (int a = g; a < Mb; a += G) {
-          const int64_t bs = ob + (((int64_t)a * Kb) << 6) + l;
-          double acc = 0.0;
-#pragma unroll 8
-          for (int j = 0; j < Kb; ++j) {
-            const int64_t e = bs + ((int64_t)j << 6);
-            acc = fma(to_d(A.P.val[e]), A.V[A.P.col[e]], acc);
+  #pragma unroll
+          for (int o = S; o < kWave; o <<= 1) {
+            const double ob2 = __shfl_xor(best, o);
+            const int oa = __shfl_xor(besta, o);
+            if (ob2 < best || (ob2 == best && oa < besta)) {
+              best = ob2;
+              besta = oa;
+            }
           }
-          candidate(a, A.cost[(int64_t)a * n + sc2] + A.gamma * acc);
-        }
-#pragma unroll
-        for (int o = S; o < kWave; o <<= 1) {
-          const double ob2 = __shfl_xor(best, o);
-          const int oa = __shfl_xor(besta, o);
-          if (ob2 < best || (ob2 == best && oa < besta)) {
-            best = ob2;
-            besta = oa;
+          if (besta >= A.m) {
+            besta = 0;
+            best = NAN;
+          }
+          if (valid && g == 0) {
+            const double phi = best - Vg[s];
+            A.r[s] = phi;
+            A.pi[s] = besta;
+            A.cpi[s] = A.cost[(int64_t)besta * n + s];
+            if (!(phi - phi == 0.0)) nonfin += 1.0;
+            pmax = fmax(pmax, fabs(phi));
+            psum = fma(phi, phi, psum);
+          }
+          const int64_t src = ob + (((int64_t)besta * Kb) << 6) + l;
+          const int64_t dst = A.Pp.off[b] + l;
+          for (int j = g; j < Kb; j += G) {
+            A.Pp.col[dst + ((int64_t)j << 6)] = A.P.col[src + ((int64_t)j << 6)];
+            A.Pp.val[dst + ((int64_t)j << 6)] = A.P.val[src + ((int64_t)j << 6)];
           }
         }
-        if (besta >= A.m) {
-          besta = 0;
-          best = NAN;
-        }
-        if (valid && g == 0) {
-          const double phi = best - A.V[s];
-          A.r[s] = phi;
-          A.pi[s] = besta;
-          A.cpi[s] = A.cost[(int64_t)besta * n + s];
-          if (!(phi - phi == 0.0)) nonfin += 1.0;
-          pmax = fmax(pmax, fabs(phi));
-          psum = fma(phi, phi, psum);
-        }
-        const int64_t src = ob + (((int64_t)besta * Kb) << 6) + l;
-        const int64_t dst = A.Pp.off[b] + l;
-        for (int j = g; j < Kb; j += G) {
-          A.Pp.col[dst + ((int64_t)j << 6)] = A.P.col[src + ((int64_t)j << 6)];
-          A.Pp.val[dst + ((int64_t)j << 6)] = A.P.val[src + ((int64_t)j << 6)];
-        }
+      };
+      if (A.vlds) {
+        for (int64_t t = threadIdx.x; t < n; t += kPB) dsm[t] = A.V[t];
+        __syncthreads();
+        rows(std::true_type{});
+      } else {
+        rows(std::false_type{});
       }
       double v[3] = {pmax, psum, nonfin};
       const int op[3] = {1, 0, 0};
@@ -756,7 +785,6 @@ leave:
 
 template <typename VT, typename XT, int G>
 ig_status launch_persist(Mdp& d, const PArgs<VT, XT>& a, int nblocks, bool coop, hipStream_t s) {
-  void* args[] = {(void*)&a};
   // the block's basis rows go to LDS when they fit beside the static LDS
   const size_t ldq = (size_t)a.spb * kSlice;
   const size_t dyn_w = 2 * ldq * sizeof(double), dyn_q = (size_t)(a.W + 1) * ldq * sizeof(XT);
@@ -767,9 +795,18 @@ ig_status launch_persist(Mdp& d, const PArgs<VT, XT>& a, int nblocks, bool coop,
                   fa.sharedSizeBytes + dyn_w + dyn_q <= (size_t)d.max_lds;
   (void)hipGetLastError();
   const void* kern = ql ? kq : kg;
-  const size_t dyn = dyn_w + (ql ? dyn_q : 0);
+  size_t dyn = dyn_w + (ql ? dyn_q : 0);
+  // V in LDS for the Bellman pass's gathers, over the same dynamic region
+  PArgs<VT, XT> av = a;
+  const size_t dyn_v = (size_t)a.n * sizeof(double);
+  hipFuncAttributes fk{};
+  av.vlds = hipFuncGetAttributes(&fk, kern) == hipSuccess &&
+            fk.sharedSizeBytes + std::max(dyn, dyn_v) <= (size_t)d.max_lds;
+  (void)hipGetLastError();
+  if (av.vlds) dyn = std::max(dyn, dyn_v);
   if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
     (void)hipGetLastError();  // not needed on every runtime; the launch reports real failures
+  void* args[] = {(void*)&av};
   ProfScope prof(d, KC_PERSIST, s);
   // A plain launch is used by the serving loop, which keeps every block of
   // all running solves co-resident by admission (cooperative launches are
