@@ -25,7 +25,7 @@ time, and under "compare" the same workload by exact-evaluation PI and by
 OPI with 20 sweeps (FP64 workloads) or with FP64 storage and arithmetic
 (mixed workloads), each timed from V0 = 0 to the same tolerance.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c4|c3|c5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c4|c3|c3-bf16|c5]
                     [--serve-requests R] [--no-serving] [--no-compare]
 """
 import argparse
@@ -51,6 +51,8 @@ WORKLOADS = {
                desc="sparse n=100 m=4 k=5 gamma=0.9 W=20 FP64, tol 1e-8, V0=0"),
     "c3": dict(cfg="c3", store="fp32", mode="mixed",
                desc="dense n=10000 m=4 gamma=0.99 W=30 FP32-stored P, mixed, tol 1e-8, V0=0"),
+    "c3-bf16": dict(cfg="c3", store="bf16", mode="mixed",
+                    desc="dense n=10000 m=4 gamma=0.99 W=30 BF16-stored P, mixed, tol 1e-8, V0=0"),
     "c4": dict(cfg="c4", store="fp32", mode="mixed",
                desc="banded sparse n=4e6 m=8 k=16 gamma=0.995 W=40 FP32 P, mixed, tol 1e-8, V0=0"),
 }
@@ -427,7 +429,7 @@ def main():
     cmp = None
     if not args.no_compare:
         print("[bench] comparisons", file=sys.stderr, flush=True)
-        runs = 5 if args.workload in ("c1", "c2", "c3") else 2
+        runs = 5 if args.workload in ("c1", "c2", "c3", "c3-bf16") else 2
         try:
             cmp = comparisons(igmres, torch, mdp, wl, restart, ms_step, runs, V_main=V.clone())
         except igmres.IgError as e:  # reported, never fatal to the main line

@@ -130,6 +130,13 @@ typedef struct {
                           future work); 0..16, 0 = none.  Stopping tests stay
                           on the true residual of J.  Stream engine only:
                           engine 0 then takes it, engine 2 is rejected.       */
+  int32_t polish;      /* igmres_pi_solve: 1 = at an outer step k >= 1 whose
+                          greedy policy equals the previous one in every
+                          state, evaluate it to min(alpha_k ||Phi_k||_inf,
+                          tol / 2) instead, so that the next outer step
+                          stops unless the policy moves again (only a
+                          smaller inexactness term: Theorem 1 still holds).
+                          Both engines; 0 = off.                              */
 } ig_params;
 
 typedef struct {
@@ -159,7 +166,7 @@ typedef struct ig_mdp_s* ig_mdp_t;
 /* Fill `p` with defaults for discount gamma: alpha = (1-gamma)/(2(1+gamma))
  * (midpoint of Theorem 1's range), restart 30, max_outer 1000,
  * max_inner 100000, tol 1e-8, FP64 mode, opi_sweeps 20, forcing 0,
- * eval_rtol 1e-13, engine 0, blocks 0, precond 0. */
+ * eval_rtol 1e-13, engine 0, blocks 0, precond 0, polish 0. */
 void ig_params_default(ig_params* p, double gamma);
 
 /* Copy P and g to the device in the GPU layout (sliced ELL, 64 states per

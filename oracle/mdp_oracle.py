@@ -42,6 +42,11 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
                            alpha_k = alpha, by the inexactness condition of
                            eq. 11 at every outer step, by residual ratios that
                            tend to zero, and by PI-LU's V*.
+                           Option polish: once the greedy policy repeats, one
+                           evaluation to tol / 2.  Pinned by identity with the
+                           plain run up to the first repeat, termination at the
+                           next outer step whenever the policy holds, and
+                           PI-LU's V*.
   neumann_apply            M^{-1} = sum_{k<=d} (gamma P^pi)^k, the truncated
                            series of Lemma 3's proof, as a right
                            preconditioner of the inner GMRES (future work
@@ -283,6 +288,7 @@ class OracleStats:
     inner_per_outer: list = field(default_factory=list)
     res_history: list = field(default_factory=list)
     alpha_history: list = field(default_factory=list)  # inner tolerance factor per outer step
+    polished: list = field(default_factory=list)  # outer steps evaluated to tol / 2
     converged: bool = False
 
 
@@ -385,21 +391,28 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
 
 
 def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inner=10_000,
-              precond=0, forcing=False):
+              precond=0, forcing=False, polish=False):
     """Algorithm 2 with outer termination at ||T V_k - V_k||_inf <= tol.
 
     alpha defaults to the midpoint of Theorem 1's admissible range,
     0.5 * (1 - gamma) / (1 + gamma).  forcing: the inner tolerance of outer
     step k uses alpha_k = min(alpha, ||T V_k - V_k||_inf^(1/2)), a forcing
     sequence tending to zero (the superlinear case of Theorem 1) instead of
-    the constant alpha.  Returns (V, pi, OracleStats); V and pi are V_k and
-    GreedyPolicy(V_k) of the terminating outer step.
+    the constant alpha.  polish: at an outer step k >= 1 whose greedy policy
+    equals the previous one in every state, the inner threshold becomes
+    min(alpha_k ||Phi_k||_inf, tol / 2): one evaluation of the (then
+    usually optimal) policy to below the outer tolerance, after which the
+    next Bellman residual meets it unless the greedy policy moves again.
+    Both only shrink the inexactness term, so Theorem 1 still applies.
+    Returns (V, pi, OracleStats); V and pi are V_k and GreedyPolicy(V_k) of
+    the terminating outer step.
     """
     g = mdp.gamma
     if alpha is None:
         alpha = 0.5 * (1 - g) / (1 + g)
     V = np.zeros(mdp.n) if V0 is None else np.asarray(V0, np.float64).copy()
     st = OracleStats()
+    pi_prev = None
     for k in range(max_outer):
         TV, pi, res = bellman(mdp, V)
         st.res_history.append(res)
@@ -408,10 +421,15 @@ def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inne
             st.outer = k
             return V, pi, st
         Phi = policy_cost(mdp, pi) - j_apply(mdp, pi, V)
+        phi_inf = float(np.max(np.abs(Phi)))
         alpha_k = min(alpha, float(np.sqrt(res))) if forcing else alpha
+        if polish and pi_prev is not None and np.array_equal(pi, pi_prev):
+            alpha_k = min(alpha_k, 0.5 * tol / phi_inf)
+            st.polished.append(k)
+        pi_prev = pi
         st.alpha_history.append(alpha_k)
-        V, info = gmres_inner(mdp, pi, V, alpha_k, W, max_inner,
-                              ref_inf=float(np.max(np.abs(Phi))), precond=precond)
+        V, info = gmres_inner(mdp, pi, V, alpha_k, W, max_inner, ref_inf=phi_inf,
+                              precond=precond)
         st.inner += info["steps"]
         st.restarts += info["restarts"]
         st.breakdowns += int(info["breakdown"])

@@ -68,6 +68,7 @@ struct PArgs {
   double alpha, tol, sqrt_n;
   int W, max_outer, max_inner, forcing;
   int vlds;  // the Bellman pass gathers V from a copy in LDS (n doubles fit)
+  int polish;  // evaluate to tol / 2 once the greedy policy repeats
   double b_bellman, b_japply, b_vec, b_resid;  // algorithmic bytes per event
 };
 
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
   for (int k = 0;; ++k) {
     // ---------------- Bellman pass: pi_k, Phi_k = T V_k - V_k, g^pi, P^pi
     {
-      double pmax = 0.0, psum = 0.0, nonfin = 0.0;
+      double pmax = 0.0, psum = 0.0, nonfin = 0.0, chg = 0.0;
       // The V gathers (m*k per state) read a copy of V in LDS when it fits: the
       // basis and product rows there are dead between inner solves.
       auto rows = [&](auto in_lds) {
@@ -515,6 +516,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
           if (valid && g == 0) {
             const double phi = best - Vg[s];
             A.r[s] = phi;
+            if (A.polish && k > 0 && A.pi[s] != besta) chg += 1.0;  // pi_{k-1} of this thread
             A.pi[s] = besta;
             A.cpi[s] = A.cost[(int64_t)besta * n + s];
             if (!(phi - phi == 0.0)) nonfin += 1.0;
@@ -536,12 +538,12 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
       } else {
         rows(std::false_type{});
       }
-      double v[3] = {pmax, psum, nonfin};
-      const int op[3] = {1, 0, 0};
-      block_reduce_big<3>(v, op, MYPART);
+      double v[4] = {pmax, psum, nonfin, chg};
+      const int op[4] = {1, 0, 0, 0};
+      block_reduce_big<4>(v, op, MYPART);
     }
     IG_BARRIER();
-    reduce_rows(PARTS, 3, 1u, red);
+    reduce_rows(PARTS, 4, 1u, red);
     if (threadIdx.x == 0) {
       sc.bellman += 1;
       sc.alg_bytes += A.b_bellman;
@@ -558,6 +560,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
       } else {
         const double alpha = A.forcing ? fmin(A.alpha, sqrt(red[0])) : A.alpha;
         sc.thr = alpha * red[0];
+        if (A.polish && k > 0 && red[3] == 0.0) sc.thr = fmin(sc.thr, 0.5 * A.tol);
         sc.beta = sqrt(red[1]);
         sc.cycle_beta = sc.beta;
         sc.steps_outer = 0;
@@ -869,6 +872,7 @@ ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coo
   a.max_outer = p.max_outer;
   a.max_inner = p.max_inner;
   a.forcing = p.forcing;
+  a.polish = p.polish;
   const double entry = d.vb + 4.0, xb = sizeof(XT);
   a.b_bellman = d.nnz * entry + d.n * (double)d.m * 8 + d.n * 28.0;
   a.b_japply = (double)d.nnz / d.m * entry + d.n * xb * 2;

@@ -928,6 +928,7 @@ void ig_params_default(ig_params* p, double gamma) {
   p->engine = 0;
   p->blocks = 0;
   p->precond = 0;
+  p->polish = 0;
 }
 
 ig_status mdp_create(const ig_mdp_desc* desc, void* stream, ig_mdp_t* out) {

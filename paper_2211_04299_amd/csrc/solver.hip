@@ -264,9 +264,17 @@ ig_status run_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stat
   if (p.engine == 2 || (p.engine == 0 && p.precond == 0 && d.coop && persistent_fits(d)))
     return persistent_igmres(d, V, pi, p, st, s);
   if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
+  // polish: pi_{k-1}, kept in the spare vector, and the Bellman pass counts
+  // the states whose greedy action differs from it (an incumbent is never
+  // preferred: tie allowance -inf)
+  int32_t* prev = reinterpret_cast<int32_t*>(d.ws.t);
   for (int k = 0;; ++k) {
     // pi_k = GreedyPolicy(V_k); Phi_k = g - J V_k = T V_k - V_k
-    if (ig_status e = bellman_pass(d, V, nullptr, pi, nullptr, 0.0, st, s)) return e;
+    const bool cmp = p.polish && k > 0;
+    if (cmp) IG_HIP(hipMemcpyAsync(prev, pi, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s));
+    if (ig_status e = bellman_pass(d, V, nullptr, pi, cmp ? prev : nullptr,
+                                   cmp ? -INFINITY : 0.0, st, s))
+      return e;
     const double res = d.hst->phi_inf;
     st.res_inf = res;
     st.outer = k;
@@ -276,8 +284,10 @@ ig_status run_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stat
     }
     if (k >= p.max_outer) return fail(IG_E_NOCONV, "max_outer reached");
     const double alpha = p.forcing ? std::min(p.alpha, std::sqrt(res)) : p.alpha;
+    double thr = alpha * res;
+    if (cmp && d.hst->changes == 0) thr = std::min(thr, 0.5 * p.tol);
     Inner in;
-    if (ig_status e = gmres_inner(d, pi, V, res, d.hst->phi_l2sq, &d.st->phi_l2sq, alpha * res,
+    if (ig_status e = gmres_inner(d, pi, V, res, d.hst->phi_l2sq, &d.st->phi_l2sq, thr,
                                   p.restart, p.max_inner, fp32, p.precond, s, in))
       return e;
     add_inner(st, in);

@@ -52,7 +52,8 @@ class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("restart", C.c_int32), ("max_outer", C.c_int32),
                 ("max_inner", C.c_int32), ("tol", C.c_double), ("mode", C.c_int),
                 ("opi_sweeps", C.c_int32), ("forcing", C.c_int32), ("eval_rtol", C.c_double),
-                ("engine", C.c_int32), ("blocks", C.c_int32), ("precond", C.c_int32)]
+                ("engine", C.c_int32), ("blocks", C.c_int32), ("precond", C.c_int32),
+                ("polish", C.c_int32)]
 
 
 class Stats(C.Structure):

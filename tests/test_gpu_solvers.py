@@ -99,6 +99,39 @@ def test_igmres_forcing_parity(name, seed, W, engine):
     assert st["outer"] <= st0["outer"]
 
 
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("name,seed,W", [("c1", 0, 20), ("c1", 2, 20), ("c2", 0, 30)])
+def test_igmres_polish_parity(name, seed, W, engine):
+    """polish=1: once the greedy policy repeats, one evaluation to tol / 2;
+    same V*, policy and outer steps as the oracle's run with polish, and no
+    more outer steps than without it."""
+    mdp, Vs, pis = reference(name, seed)
+    tol = tol_par(mdp, np.max(np.abs(Vs)))
+    V, pi, st = solve(mdp, tol=tol, restart=W, engine=engine, polish=1)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+    Vo, pio, sto = O.igmres_pi(mdp, W=W, tol=tol, polish=True)
+    assert sto.polished
+    assert st["outer"] == sto.outer
+    assert abs(st["inner"] - sto.inner) <= sto.outer
+    _, _, st0 = solve(mdp, tol=tol, restart=W, engine=engine)
+    assert st["outer"] <= st0["outer"]
+
+
+def test_igmres_polish_dense_mixed():
+    """The stream engine's dense Bellman kernels count policy changes too."""
+    mdp = synth.dense_exp(300, 4, 0.99, seed=5)
+    stored = mdp.with_values(P=synth.upcast_values(synth.round_values(mdp.P, "fp32"), "fp32"))
+    Vs, pis, _ = O.policy_iteration(stored)
+    tol = tol_par(stored, np.max(np.abs(Vs)))
+    V, pi, st = solve(mdp, store="fp32", mode="mixed", tol=tol, restart=20, polish=1)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-6
+    Vo, _, sto = O.igmres_pi(stored, W=20, tol=tol, polish=True)
+    assert sto.polished and st["outer"] == sto.outer
+
 def test_ipi_vi_forcing_c1():
     mdp, Vs, pis = reference("c1", 1)
     V, pi, st = solve(mdp, method="ipi_vi_solve", tol=1e-10, forcing=1)

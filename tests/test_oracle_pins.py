@@ -492,3 +492,37 @@ def test_forcing_superlinear_and_optimal(seed):
     assert ratios_f[-1] < ratios_f[0] and ratios_f[-1] < 1e-3
     assert np.min(ratios_0) > 10 * ratios_f[-1]
     assert st.outer <= st0.outer
+
+
+# --- polish: one evaluation to tol / 2 once the greedy policy repeats ---
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_polish_prefix_termination_and_optimum(seed):
+    mdp = synth.config("c1", seed)
+    Vs, pis, _ = O.policy_iteration(mdp)
+    tol = 1e-11 * np.max(np.abs(Vs))
+    V, pi, st = O.igmres_pi(mdp, W=20, tol=tol, polish=True)
+    V0, _, st0 = O.igmres_pi(mdp, W=20, tol=tol)
+    assert st.converged and st.polished
+    # the same run as plain Algorithm 2 until the first repeated policy
+    p0 = st.polished[0]
+    assert st.res_history[:p0 + 1] == st0.res_history[:p0 + 1]
+    Va, _, _ = O.igmres_pi(mdp, W=20, tol=0.0, max_outer=p0, polish=True)
+    Vb, _, _ = O.igmres_pi(mdp, W=20, tol=0.0, max_outer=p0)
+    np.testing.assert_array_equal(Va, Vb)
+    # the polished evaluation meets tol / 2 on its own policy, and the
+    # following Bellman residual meets tol while the policy holds
+    k = st.polished[-1]
+    Vk, pik, _ = O.igmres_pi(mdp, W=20, tol=0.0, max_outer=k, polish=True)
+    Vn, pin, _ = O.igmres_pi(mdp, W=20, tol=0.0, max_outer=k + 1, polish=True)
+    _, pik, _ = O.bellman(mdp, Vk)
+    r = np.max(np.abs(O.policy_cost(mdp, pik) - O.j_apply(mdp, pik, Vn)))
+    assert r <= 0.5 * tol * (1 + 1e-12)
+    _, pi_next, res_next = O.bellman(mdp, Vn)
+    if np.array_equal(pi_next, pik):
+        assert res_next <= tol and st.outer == k + 1
+    # optimum, in no more outer steps than the plain run
+    assert np.max(np.abs(V - Vs)) <= 1e-9 * np.max(np.abs(Vs))
+    sel = O.action_gaps(mdp, Vs) > 1e-9
+    assert np.array_equal(pi[sel], pis[sel])
+    assert st.outer <= st0.outer
