@@ -69,3 +69,32 @@ def test_c3_dense_full_size(store):
     _, _, res64 = O.bellman(mdp, out[0])
     print(f"c3 {store}: outer={out[2]['outer']} inner={out[2]['inner']} time_ms={out[2]['time_ms']:.1f} "
           f"rel_error_bound(stored MDP)={rb:.2e} residual on the FP64 MDP={res64:.2e}")
+
+
+def test_persistent_engine_at_its_largest_shape():
+    """2^19 states: 256 workgroups of 32 slices, the largest grid the
+    persistent engine takes (every CU holds one workgroup); checked by the
+    certificate on the CPU.  One slice more no longer fits that engine
+    (refused when asked for) and the automatic choice takes the stream
+    engine instead, with the same result."""
+    I = igm()
+    n = 1 << 19
+    mdp = synth.sparse_uniform(n, 2, 4, 0.95, seed=11)
+    tol = 1e-9
+    with I.mdp_create(mdp) as h:
+        V, pi = zeros(n), zeros(n, "int32")
+        st = h.igmres_pi_solve(V, pi, I.params_default(mdp.gamma, tol=tol, restart=20, engine=2))
+        Vh, pih = host(V), host(pi)
+    TV, pio, res = O.bellman(mdp, Vh)
+    check(mdp, Vh, pih, st, mdp, TV, pio, res, tol)
+    big = synth.sparse_uniform(n + 64, 2, 4, 0.95, seed=11)
+    with I.mdp_create(big) as h:
+        V, pi = zeros(big.n), zeros(big.n, "int32")
+        with pytest.raises(I.IgError) as ei:
+            h.igmres_pi_solve(V, pi, I.params_default(big.gamma, tol=tol, restart=20, engine=2))
+        assert ei.value.status == I.IG_E_TOO_LARGE
+        V.zero_()
+        st = h.igmres_pi_solve(V, pi, I.params_default(big.gamma, tol=tol, restart=20))
+        Vb, pib = host(V), host(pi)
+    TV, pio, res = O.bellman(big, Vb)
+    check(big, Vb, pib, st, big, TV, pio, res, tol)

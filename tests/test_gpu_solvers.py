@@ -245,3 +245,33 @@ def test_noconv_and_bad_params(engine):
         with pytest.raises(I.IgError) as e:
             solve(mdp, **kw)
         assert e.value.status == code
+
+
+@pytest.mark.parametrize("W,engine", [(1, 1), (1, 2), (2, 1), (2, 2), (64, 1), (64, 2), (128, 1)])
+def test_restart_extremes(W, engine):
+    """GMRES(1) and GMRES(2) (restart after every one or two steps), the
+    persistent engine's cap of 64 and the interface's cap of 128 columns:
+    V*, the optimal policy and the outer steps of the oracle's Algorithm 2
+    with the same W."""
+    mdp = synth.config("c1", 1) if W <= 2 else synth.sparse_uniform(3000, 4, 8, 0.99, seed=12)
+    Vs, pis, _ = O.policy_iteration(mdp)
+    tol = tol_par(mdp, np.max(np.abs(Vs)))
+    V, pi, st = solve(mdp, tol=tol, restart=W, engine=engine)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+    Vo, _, sto = O.igmres_pi(mdp, W=W, tol=tol)
+    assert st["outer"] == sto.outer
+    if W <= 2:
+        assert st["restarts"] > 0
+
+
+def test_restart_caps_rejected():
+    I = igm()
+    mdp = synth.config("c1", 0)
+    for W, engine in [(65, 2), (129, 1), (129, 0), (0, 1)]:
+        with I.mdp_create(mdp) as h:
+            V, pi = zeros(mdp.n), zeros(mdp.n, "int32")
+            with pytest.raises(I.IgError) as ei:
+                h.igmres_pi_solve(V, pi, I.params_default(mdp.gamma, restart=W, engine=engine))
+            assert ei.value.status == (I.IG_E_INVALID if W == 0 else I.IG_E_TOO_LARGE)
