@@ -6,6 +6,7 @@
 // with shuffles; the block picks the (value, action)-lexicographic minimum.
 // Products with P^pi: one wavefront per state on row (s, pi(s)).
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "internal.hpp"
@@ -586,10 +587,16 @@ void launch_bellman_dense(Mdp& d, const double* V, double* TV, double* Phi, int3
                              (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi, pi_old,
                              tie_abs, d.cpi, d.part, (const uint8_t*)d.adm);
         };
-        // two states, four actions each, two loads per row and lane in
-        // flight (the best of 1-8 states x 1-4 actions x 1-4 loads measured
-        // on c3: 264 against 322 us for one state x four actions x four loads)
-        go(k_bellman_dense4<VT, 2, 4, 2>, 2);
+        // FP64/FP32: two states, four actions each, two loads per row and
+        // lane in flight (the best of 1-8 states x 1-4 actions x 1-4 loads
+        // measured on c3: 264 against 322 us for one state x four actions x
+        // four loads).  BF16, whose 16-byte loads carry eight values to widen
+        // each: four states x four actions, one load per row (157 against
+        // 172 us on c3; FP32 and FP64 are slower that way)
+        if constexpr (std::is_same<VT, bf16>::value)
+          go(k_bellman_dense4<VT, 4, 4, 1>, 4);
+        else
+          go(k_bellman_dense4<VT, 2, 4, 2>, 2);
       } else
         hipLaunchKernelGGL(k_bellman_dense<VT>, dim3(grid_states(d.n)), dim3(kBlock), 0, s,
                            (const VT*)d.P, (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi,
