@@ -313,8 +313,8 @@ def serving_leg(igmres, synth, torch, count, seed, load=0.8, prep_threads=4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c5"])
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--prep-threads", type=int, default=4)
