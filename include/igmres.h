@@ -119,7 +119,11 @@ typedef struct {
                           step (any size, dense or sparse), 2 a single
                           persistent launch for the whole solve (sparse,
                           up to 256*32 slices of 64 states); auto picks 2
-                          when it applies                                     */
+                          when it applies.  Engine 2's grid barriers wait
+                          a bounded number of polls (environment variable
+                          IG_SPIN_LIMIT overrides, for tests of the error
+                          path); a wait that runs out ends the solve with
+                          IG_E_DEVICE after every workgroup has left.       */
   int32_t blocks;      /* persistent engine: workgroups of the launch (0 =
                           from the shape); clamped so that a workgroup owns
                           1..32 slices.  The result depends on this count

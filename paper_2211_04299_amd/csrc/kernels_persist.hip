@@ -43,7 +43,7 @@ constexpr int kPMaxSpb = 32;         // slices per block
 constexpr int kPMaxOwn = kPMaxSpb * kSlice;
 constexpr int kPMaxW = 64;           // restart cap of this engine (LDS Givens state)
 constexpr int kPStride = kPMaxW + 8; // doubles per block row of partials
-constexpr long kSpinLimit = 1L << 23;
+constexpr long kSpinLimit = 1L << 23;  // polls per barrier wait (IG_SPIN_LIMIT overrides)
 
 template <typename VT, typename XT>
 struct PArgs {
@@ -69,6 +69,7 @@ struct PArgs {
   int W, max_outer, max_inner, forcing;
   int vlds;  // the Bellman pass gathers V from a copy in LDS (n doubles fit)
   int polish;  // evaluate to tol / 2 once the greedy policy repeats
+  long spin_limit;  // polls before a barrier wait fails
   double b_bellman, b_japply, b_vec, b_resid;  // algorithmic bytes per event
 };
 
@@ -107,7 +108,7 @@ __device__ __forceinline__ unsigned ld_flag(const unsigned* p) {
 // bad: two LDS words, zero at launch, used by barrier parity; each barrier
 // clears the word of the next one (all threads read it before this barrier).
 __device__ __forceinline__ bool gbarrier(unsigned int* flags, PCtl* ctl, unsigned epoch,
-                                         int* bad) {
+                                         int* bad, long spin_limit) {
   __syncthreads();
   if (gridDim.x == 1) return true;  // one block: the block barrier orders everything
   if (threadIdx.x == 0) {
@@ -118,7 +119,7 @@ __device__ __forceinline__ bool gbarrier(unsigned int* flags, PCtl* ctl, unsigne
     long spins = 0;
     while (ld_flag(&flags[threadIdx.x]) < epoch) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
+      if (++spins > spin_limit) {
         __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         bad[epoch & 1] = 1;
         break;
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
     __syncthreads();
     own_axpy<XT>(Qv, nown, cols, coef, 1.0, psum, [&](int t) { return A.Vb[s_lo + t]; },
                  [&](int t, double v) { A.V[s_lo + t] = v; });
-    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad)) return false;
+    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad, A.spin_limit)) return false;
     {
       double pmax = 0.0, ps = 0.0;
       for (int64_t base = s_lo + (int64_t)wid * S; base < s_hi; base += SPR) {
@@ -447,7 +448,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
       const int op[2] = {1, 0};
       block_reduce_big<2>(v, op, MYPART);
     }
-    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad)) return false;
+    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad, A.spin_limit)) return false;
     reduce_rows(PARTS, 2, 1u, red);
     if (threadIdx.x == 0) {
       sc.alg_bytes += A.b_resid + A.b_vec * (cols + 2.0);
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
 
 #define IG_BARRIER()                                    \
   do {                                                  \
-    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad)) goto leave; \
+    if (!gbarrier(A.flags, A.ctl, ++epoch, s_bad, A.spin_limit)) goto leave; \
   } while (0)
 
   for (int k = 0;; ++k) {
@@ -873,6 +874,9 @@ ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coo
   a.max_inner = p.max_inner;
   a.forcing = p.forcing;
   a.polish = p.polish;
+  // the error path of the barrier wait can be exercised with a tiny limit
+  const char* sl = std::getenv("IG_SPIN_LIMIT");
+  a.spin_limit = sl ? std::max(0L, std::atol(sl)) : kSpinLimit;
   const double entry = d.vb + 4.0, xb = sizeof(XT);
   a.b_bellman = d.nnz * entry + d.n * (double)d.m * 8 + d.n * 28.0;
   a.b_japply = (double)d.nnz / d.m * entry + d.n * xb * 2;

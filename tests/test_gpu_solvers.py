@@ -1,6 +1,8 @@
 """igmres_pi_solve, pi_solve, opi_solve and ipi_vi_solve against V* and pi*
 of the FP64 oracle (PI with dense LU evaluation, pinned by brute force and
 closed forms), plus iteration counts of the literal Algorithm 2."""
+import os
+
 import numpy as np
 import pytest
 
@@ -275,3 +277,30 @@ def test_restart_caps_rejected():
             with pytest.raises(I.IgError) as ei:
                 h.igmres_pi_solve(V, pi, I.params_default(mdp.gamma, restart=W, engine=engine))
             assert ei.value.status == (I.IG_E_INVALID if W == 0 else I.IG_E_TOO_LARGE)
+
+
+def test_barrier_wait_limit_drains_and_reports():
+    """Failure handling of the persistent engine, forced from the host: with
+    a limit of zero polls per grid-barrier wait, a block that has to wait
+    gives up and leaves; every other block leaves at its next barrier, so the
+    launch ends, the call reports IG_E_DEVICE, and the next solve on the
+    same handle is exact."""
+    I = igm()
+    mdp, Vs, pis = reference("c2", 0)
+    with I.mdp_create(mdp) as h:
+        V, pi = zeros(mdp.n), zeros(mdp.n, "int32")
+        p = I.params_default(mdp.gamma, restart=30, engine=2)
+        os.environ["IG_SPIN_LIMIT"] = "0"
+        try:
+            with pytest.raises(I.IgError) as ei:
+                h.igmres_pi_solve(V, pi, p)
+        finally:
+            del os.environ["IG_SPIN_LIMIT"]
+        assert ei.value.status == I.IG_E_DEVICE
+        assert "barrier" in I.last_error()
+        V.zero_()
+        st = h.igmres_pi_solve(V, pi, p)
+        Vh, pih = host(V), host(pi)
+    assert st["converged"] == 1
+    assert rel_err(Vh, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pih)
