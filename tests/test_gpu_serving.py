@@ -8,6 +8,7 @@ resolvable.  Batch invariance: each request's result is bitwise the same
 served alone, in a mix, and through the direct persistent entry point with
 the same workgroup count."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -235,3 +236,26 @@ def test_serving_storage_and_modes_mix():
             assert np.array_equal(Vs, host(V)), (store, mode)
             assert np.array_equal(pis, host(pi)), (store, mode)
         assert sts["converged"] == 1
+
+
+def test_serving_barrier_wait_limit():
+    """A request whose grid-barrier wait runs out (limit of zero polls,
+    forced from the host) fails alone with IG_E_DEVICE; a one-workgroup
+    request beside it needs no grid barrier and is served exactly, and the
+    server keeps serving once the limit is back."""
+    I = igm()
+    wide, small = request_mdp(MIX[2]), request_mdp(MIX[4])
+    with I.Server(max_states=50000) as srv:
+        os.environ["IG_SPIN_LIMIT"] = "0"
+        try:
+            tw = srv.submit(wide, params(wide))
+            ts = srv.submit(small, params(small))
+            with pytest.raises(I.IgError) as ei:
+                srv.result(tw)
+            Vs, pis, sts = srv.result(ts)
+        finally:
+            del os.environ["IG_SPIN_LIMIT"]
+        assert ei.value.status == I.IG_E_DEVICE
+        certify(small, Vs, pis, sts)
+        V, pi, st = srv.result(srv.submit(wide, params(wide)))
+        certify(wide, V, pi, st)
