@@ -78,7 +78,8 @@ design notes of the repository):
     residual that produced the current first basis vector, and the update
     "V_{k+1} <- Q y + V_k" adds to the iterate at the start of the current
     restart cycle;
-  * "go to line 35" ends the inner loop and proceeds to the next outer step;
+  * the jump of Algorithm 2's lucky-breakdown branch ends the inner loop and
+    proceeds to the next outer step;
   * Phi_k = 0 (or a zero restart residual) means the inner loop is not entered;
   * the least-squares problem uses the leading (i+1) x i block of H;
   * infinity-norm in every stopping test, 2-norm inside GMRES.
