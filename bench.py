@@ -340,7 +340,7 @@ def main():
         print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "copies": 5}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(a solve would shard by contiguous state blocks with all-gathers and all-reduces)", file=sys.stderr)
         sys.exit(2)
 
