@@ -109,9 +109,10 @@ typedef struct {
   double tol;          /* outer stop: ||T V - V||_inf <= tol (absolute)       */
   ig_mode mode;
   int32_t opi_sweeps;  /* opi_solve: applications of T^pi per outer step      */
-  int32_t forcing;     /* 0: alpha_k = alpha (Algorithm 2); 1: alpha_k =
-                          min(alpha, sqrt(||T V_k - V_k||_inf)) (a forcing
-                          sequence tending to zero, Theorem 1)                 */
+  int32_t forcing;     /* igmres_pi_solve and ipi_vi_solve: 0: alpha_k =
+                          alpha (Algorithm 2); 1: alpha_k = min(alpha,
+                          sqrt(||T V_k - V_k||_inf)) (a forcing sequence
+                          tending to zero, Theorem 1)                          */
   double eval_rtol;    /* pi_solve: evaluation residual target relative to
                           max |g(s,a)| (exact evaluation taken as GMRES to
                           this level or to stagnation)                        */
