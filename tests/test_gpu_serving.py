@@ -94,19 +94,22 @@ def test_serving_batch_invariance_and_certificate():
         assert st["latency_ms"] >= st["queue_ms"] >= 0.0
 
 
-@pytest.mark.parametrize("spec", [MIX[0], MIX[2]])
-def test_serving_matches_direct_persistent_solve(spec):
+@pytest.mark.parametrize("spec,opts", [(MIX[0], {}), (MIX[2], {}),
+                                       (MIX[3], {"forcing": 1, "polish": 1})])
+def test_serving_matches_direct_persistent_solve(spec, opts):
     """Same kernel, same workgroup count: the served result equals the
-    direct igmres_pi_solve (cooperative launch, engine 2) bit for bit."""
+    direct igmres_pi_solve (cooperative launch, engine 2) bit for bit, also
+    with the forcing sequence and polish options."""
     I = igm()
     mdp = request_mdp(spec)
     blocks = math.ceil(math.ceil(mdp.n / 64) / BLOCK_SLICES)
     with I.Server(block_slices=BLOCK_SLICES) as srv:
-        Vs, pis, sts = srv.result(srv.submit(mdp, params(mdp)))
+        Vs, pis, sts = srv.result(srv.submit(mdp, params(mdp, **opts)))
+    certify(mdp, Vs, pis, sts)
     with I.mdp_create(mdp, store="fp32") as h:
         V = zeros(mdp.n)
         pi = zeros(mdp.n, "int32")
-        st = h.igmres_pi_solve(V, pi, params(mdp, engine=2, blocks=blocks))
+        st = h.igmres_pi_solve(V, pi, params(mdp, engine=2, blocks=blocks, **opts))
         Vd, pid = host(V), host(pi)
     assert np.array_equal(Vs, Vd)
     assert np.array_equal(pis, pid)
