@@ -96,3 +96,19 @@ def test_precond_rejected_by_persistent_engine():
             h.igmres_pi_solve(zeros(mdp.n), zeros(mdp.n, "int32"),
                               I.params_default(mdp.gamma, engine=2, precond=1))
         assert e.value.status == I.IG_E_INVALID
+
+
+@pytest.mark.parametrize("name,W", [("c1", 20), ("c2", 30)])
+def test_precond_with_forcing_and_polish(name, W):
+    """The options compose: the preconditioned inner solve under the forcing
+    sequence and polish gives V*, the optimal policy and the outer steps of
+    the oracle's run with the same three options."""
+    mdp, Vs, pis = reference(name)
+    tol = tol_par(mdp, np.max(np.abs(Vs)))
+    V, pi, st = solve(mdp, tol=tol, restart=W, precond=2, forcing=1, polish=1)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
+    _, _, sto = O.igmres_pi(mdp, W=W, tol=tol, precond=2, forcing=True, polish=True)
+    assert st["outer"] == sto.outer
+    assert abs(st["inner"] - sto.inner) <= sto.outer
