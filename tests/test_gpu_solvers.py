@@ -304,3 +304,20 @@ def test_barrier_wait_limit_drains_and_reports():
     assert st["converged"] == 1
     assert rel_err(Vh, Vs) <= 1e-8
     assert_policy_match(mdp, Vs, pis, pih)
+
+
+@pytest.mark.parametrize("store", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("method", ["pi_solve", "opi_solve", "ipi_vi_solve"])
+def test_other_solvers_dense(method, store):
+    """PI (policy gather and evaluation), OPI and inexact PI with VI sweeps on
+    dense transition data: V* and the optimal policy of the stored MDP."""
+    mdp = synth.dense_exp(400, 4, 0.99, seed=7)
+    stored = mdp if store == "fp64" else mdp.with_values(
+        P=synth.upcast_values(synth.round_values(mdp.P, store), store))
+    Vs, pis, _ = O.policy_iteration(stored)
+    tol = tol_par(stored, np.max(np.abs(Vs)))
+    mode = "fp64" if store == "fp64" else "mixed"
+    V, pi, st = solve(mdp, method=method, store=store, mode=mode, tol=tol, opi_sweeps=20)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= (1e-8 if store == "fp64" else 1e-6)
+    assert_policy_match(stored, Vs, pis, pi)
