@@ -694,10 +694,16 @@ void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double*
     by_store(d, [&](auto t) {
       using VT = decltype(t);
       if (vec_ok(d)) {
-        auto kern = k_policy_pass_dense_g<VT, 1, 4, 4>;
-        nb = grid_rounds((d.n + 3) / 4, resident_blocks(d, kern));
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n, d.gamma,
-                           pi, (const double*)d.cpi, Vin, Vout, d.part);
+        // the shapes of the FP64 residual above
+        auto go = [&](auto kern) {
+          nb = grid_rounds((d.n + 3) / 4, resident_blocks(d, kern));
+          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, s, (const VT*)d.P, d.m, d.n,
+                             d.gamma, pi, (const double*)d.cpi, Vin, Vout, d.part);
+        };
+        if constexpr (std::is_same<VT, double>::value)
+          go(k_policy_pass_dense_g<VT, 1, 4, 4>);
+        else
+          go(k_policy_pass_dense_g<VT, 1, 4, 1>);
       } else {
         hipLaunchKernelGGL((k_policy_pass_dense<VT, 1>), dim3(nb), dim3(kBlock), 0, s,
                            (const VT*)d.P, d.m, d.n, d.gamma, pi, (const double*)d.cpi, Vin, Vout,
