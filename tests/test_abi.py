@@ -68,3 +68,4 @@ def test_params_default_is_theorem1_midpoint():
     p = igmres.params_default(0.99)
     assert p.alpha == pytest.approx(0.5 * 0.01 / 1.99)
     assert p.restart == 30 and p.tol == 1e-8 and p.mode == igmres.IG_MODE_FP64
+    assert p.forcing == 0 and p.polish == 0 and p.precond == 0 and p.engine == 0
