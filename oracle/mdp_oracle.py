@@ -29,11 +29,18 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
   value_iteration          VI, eq. 6 with its gamma-contraction stopping bound.
   brute_force              V* = componentwise min over all deterministic
                            policies (eq. 2).
-  gmres_inner, igmres_pi   Algorithm 2 (GMRES(W) policy iteration) in the
-                           paper's order, with the readings listed below.
-                           Pinned by the GMRES minimum-residual property
-                           (eq. 13) computed from an explicitly formed Krylov
-                           matrix, by agreement with LU at alpha -> 0, and by
+  gmres_inner              the inner solver of Algorithm 2 written from
+                           the definition of the restarted GMRES(W) iterate
+                           (minimum residual over x_c + K_i, eq. 13), not
+                           from the printed pseudo-code: a Householder-QR
+                           basis of K_i and a direct least-squares solve
+                           over J times it.  Pinned by the minimum-residual
+                           property against an explicitly formed power-basis
+                           Krylov matrix, by LU at alpha -> 0, by the
+                           <= 2 steps of uniform transitions and the exactly
+                           n steps of the deterministic n-cycle (Lemma 1).
+  igmres_pi                Algorithm 2's outer loop (greedy policy,
+                           Phi_k, inexact evaluation).  Pinned by
                            agreement of the returned V with PI-LU's V*.
                            Option forcing: alpha_k = min(alpha,
                            ||T V_k - V_k||_inf^(1/2)), a forcing sequence that
@@ -55,7 +62,11 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
                            residual property over x0 + M^{-1} K_i(J M^{-1}, r0)
                            and by degree 0 = plain GMRES.
   opi                      optimistic PI with a fixed number of VI sweeps
-                           (Sec. 2.1); OPI(1) is VI.
+                           (Sec. 2.1).  Pinned by OPI(1) = VI, by a
+                           hand-derived OPI(2) trajectory on the two-state
+                           example (tests/golden) and by the W -> infinity
+                           limit: the policy sequence and iteration count of
+                           exact PI.
   certificate              ||V - V*||_inf <= ||TV - V||_inf / (1 - gamma),
                            from gamma-contraction (Sec. 2).
   action sets A(s)         every minimum runs over the admissible actions of
@@ -221,12 +232,15 @@ def policy_eval_neumann(mdp, pi, rel=1e-15, max_terms=1_000_000):
 # plain dynamic programming (Section 2.1, eq. 2)
 # ---------------------------------------------------------------------------
 
-def policy_iteration(mdp, V0=None, max_iter=1000):
+def policy_iteration(mdp, V0=None, max_iter=1000, trace=None):
     """Exact PI: pi_0 = GreedyPolicy(V0), then alternate LU evaluation and
-    improvement until the policy repeats.  Returns (V, pi, iterations)."""
+    improvement until the policy repeats.  Returns (V, pi, iterations);
+    a list passed as `trace` receives the evaluated policies in order."""
     V = np.zeros(mdp.n) if V0 is None else np.asarray(V0, np.float64)
     _, pi, _ = bellman(mdp, V)
     for it in range(1, max_iter + 1):
+        if trace is not None:
+            trace.append(pi.copy())
         V = policy_eval_lu(mdp, pi)
         new = greedy_keep(mdp, V, pi)
         if np.array_equal(new, pi):
@@ -293,102 +307,89 @@ class OracleStats:
     converged: bool = False
 
 
-def _lsq(H, i, beta):
-    """argmin_y || beta e_1 - H[:i+1, :i] y ||_2  (leading block of H)."""
-    rhs = np.zeros(i + 1)
-    rhs[0] = beta
-    y, *_ = np.linalg.lstsq(H[:i + 1, :i], rhs, rcond=None)
-    return y
-
-
 def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=False, precond=0):
-    """The inner while-loop of Algorithm 2 for J = I - gamma P^pi, b = g^pi.
+    """Inexact policy evaluation by restarted GMRES(W): the inner solver of
+    Algorithm 2 (Sec. 3.1) for J V = b with J = I - gamma P^pi, b = g^pi.
 
-    Starting at x0, runs restarted GMRES(W) (Arnoldi with modified
-    Gram-Schmidt, a least-squares solve on the Hessenberg matrix, explicit
-    residual test every step) until
+    Written from the definition of the GMRES iterate (Sec. 2.2, eq. 13), not
+    from the printed pseudo-code: inside a restart cycle that starts at x_c
+    with residual r_c = b - J x_c, the i-th iterate is
+
+        x_i = x_c + M^{-1} z_i,  z_i = argmin_{z in K_i} ||r_c - J M^{-1} z||_2,
+        K_i = span{r_c, A r_c, ..., A^{i-1} r_c},  A = J M^{-1},
+
+    (M^{-1} = identity unless precond = d > 0 selects the degree-d Neumann
+    polynomial of neumann_apply, a right preconditioner: the future work of
+    Sec. 5).  A cycle ends after W iterates and the next one starts from the
+    last iterate.  The loop returns the first iterate that meets the inexact
+    rule of eq. 11 in the infinity-norm,
         || b - J x ||_inf <= alpha * ref_inf,
     where ref_inf defaults to ||b - J x0||_inf (= ||Phi_k||_inf).
-    Two guards the paper leaves implicit end the loop early: max_inner
-    Arnoldi steps, and a whole restart cycle that lowers the residual 2-norm
+
+    Steps (plain library primitives, no fusion):
+      * an orthonormal basis of K_{i+1} is the basis of K_i plus the last
+        column of the Q factor of a Householder QR (numpy.linalg.qr) of
+        [basis of K_i, A q_i], q_i the newest basis vector
+        (K_{i+1} = K_i + span{A q_i});
+      * z_i solves the least-squares problem over the n x i matrix
+        [A q_1, ..., A q_i] directly (numpy.linalg.lstsq);
+      * the residual b - J x_i is formed explicitly at every step.
+    When A q_i lies in K_i (the R factor's new diagonal entry is exactly
+    zero) the space is invariant, x_i is the exact solution and the loop
+    ends (the lucky breakdown; the paper then proceeds to the next outer
+    step).  Two guards the paper leaves implicit end the loop early:
+    max_inner iterates, and a restart cycle that lowers the residual 2-norm
     (the quantity GMRES minimises) by less than a factor 1 - 1e-6: restarted
     GMRES(W) with W < n can stagnate completely, and rounding puts a floor
     under the residual.
-    precond = d > 0 runs right-preconditioned GMRES with M^{-1} the degree-d
-    Neumann polynomial (neumann_apply): Arnoldi on J M^{-1}, iterates
-    x = x_cycle + M^{-1} Q y.  The residual it minimises and the stopping
-    test stay those of J itself (the preconditioner the paper names as
-    future work, Sec. 5; this polynomial is one choice).
-    Returns (x, info) with info = dict(steps, restarts, breakdown, H_first,
-    iterates (if trace), res_inf).
+    Returns (x, info) with info = dict(steps, restarts, breakdown, iterates
+    (first cycle, if trace), res_inf, thr, stagnated).
     """
-    n = mdp.n
     Ppi = policy_matrix_sparse(mdp, pi)
     b = policy_cost(mdp, pi)
     J = lambda v: j_apply(mdp, pi, v, Ppi)  # noqa: E731
     Minv = lambda v: neumann_apply(mdp, pi, v, precond, Ppi)  # noqa: E731
+    A = lambda v: J(Minv(v))  # noqa: E731
 
-    x_cycle = np.asarray(x0, np.float64).copy()   # iterate at the cycle start
-    x = x_cycle.copy()
+    x = np.asarray(x0, np.float64).copy()
     r = b - J(x)
+    res_inf = float(np.max(np.abs(r))) if r.size else 0.0
     if ref_inf is None:
-        ref_inf = float(np.max(np.abs(r)))
+        ref_inf = res_inf
     thr = alpha * ref_inf
-    beta = float(np.linalg.norm(r))
-    Q = np.zeros((n, W + 1))
-    H = np.zeros((W + 1, W))
-    if beta > 0:
-        Q[:, 0] = r / beta
-    i = 0          # number of Arnoldi columns built in this cycle
     steps = restarts = 0
-    breakdown = False
-    H_first = None
+    breakdown = stagnated = False
     iterates = []
-    res_inf = float(np.max(np.abs(r)))
-    stagnated = False
-    while res_inf > thr and steps < max_inner:
-        q = J(Minv(Q[:, i]))
-        for j in range(i + 1):                    # modified Gram-Schmidt
-            H[j, i] = Q[:, j] @ q
-            q = q - H[j, i] * Q[:, j]
-        H[i + 1, i] = np.linalg.norm(q)
-        steps += 1
-        if H[i + 1, i] == 0.0:                    # lucky breakdown
-            y = _lsq(H, i + 1, beta)
-            x = x_cycle + Minv(Q[:, :i + 1] @ y)
-            breakdown = True
-            res_inf = float(np.max(np.abs(b - J(x))))
-            if trace:
+    while res_inf > thr and steps < max_inner and not (breakdown or stagnated):
+        # one restart cycle from x_c = x, r_c = r
+        x_c, r_c = x.copy(), r.copy()
+        beta = float(np.linalg.norm(r_c))
+        basis = (r_c / beta)[:, None]      # orthonormal basis of K_1
+        AK = np.zeros((mdp.n, 0))          # A applied to the basis vectors
+        for _ in range(W):
+            AK = np.column_stack([AK, A(basis[:, -1])])
+            z, *_ = np.linalg.lstsq(AK, r_c, rcond=None)
+            x = x_c + Minv(basis @ z)
+            r = b - J(x)
+            res_inf = float(np.max(np.abs(r)))
+            steps += 1
+            if trace and restarts == 0:
                 iterates.append(x.copy())
-            break
-        Q[:, i + 1] = q / H[i + 1, i]
-        y = _lsq(H, i + 1, beta)
-        x = x_cycle + Minv(Q[:, :i + 1] @ y)
-        if trace and restarts == 0:
-            iterates.append(x.copy())
-        r = b - J(x)
-        res_inf = float(np.max(np.abs(r)))
-        if i + 1 == W:                            # restart from the new residual
-            if restarts == 0:
-                H_first = H.copy()
-            restarts += 1
-            Q[:] = 0.0
-            H[:] = 0.0
-            beta_prev = beta
-            beta = float(np.linalg.norm(r))
-            if beta > 0:
-                Q[:, 0] = r / beta
-            x_cycle = x.copy()
-            i = 0
-            if res_inf > thr and beta > (1.0 - 1e-6) * beta_prev:
-                stagnated = True
+            if res_inf <= thr or steps >= max_inner:
                 break
+            Qf, Rf = np.linalg.qr(np.column_stack([basis, AK[:, -1]]))
+            if Rf[-1, -1] == 0.0:          # K_{i+1} = K_i: x is exact
+                breakdown = True
+                break
+            # the new direction, orthogonal to K_i; the earlier columns stay
+            # as they are (AK holds A times exactly these vectors)
+            basis = np.column_stack([basis, Qf[:, -1]])
         else:
-            i += 1
-    if H_first is None:
-        H_first = H.copy()
-    return x, dict(steps=steps, restarts=restarts, breakdown=breakdown, H_first=H_first,
-                   iterates=iterates, res_inf=res_inf, thr=thr, stagnated=stagnated)
+            restarts += 1
+            if res_inf > thr and float(np.linalg.norm(r)) > (1.0 - 1e-6) * beta:
+                stagnated = True
+    return x, dict(steps=steps, restarts=restarts, breakdown=breakdown, iterates=iterates,
+                   res_inf=res_inf, thr=thr, stagnated=stagnated)
 
 
 def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inner=10_000,
@@ -441,14 +442,17 @@ def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inne
     return V, pi, st
 
 
-def opi(mdp, sweeps, tol=1e-8, V0=None, max_outer=10_000_000):
+def opi(mdp, sweeps, tol=1e-8, V0=None, max_outer=10_000_000, trace=None):
     """Optimistic PI: greedy policy from V_k, then `sweeps` applications of
     T^{pi_k} (the first of which equals T V_k); stop at ||T V - V||_inf <= tol.
-    Returns (V, pi, outer, total_sweeps)."""
+    Returns (V, pi, outer, total_sweeps); a list passed as `trace` receives
+    the greedy policy of every outer step."""
     V = np.zeros(mdp.n) if V0 is None else np.asarray(V0, np.float64).copy()
     total = 0
     for k in range(max_outer):
         TV, pi, res = bellman(mdp, V)
+        if trace is not None:
+            trace.append(pi.copy())
         if res <= tol:
             return V, pi, k, total
         Ppi = policy_matrix_sparse(mdp, pi)

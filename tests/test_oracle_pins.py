@@ -266,6 +266,46 @@ def test_opi_one_sweep_is_vi(small):
     np.testing.assert_array_equal(TVo, Vv)
 
 
+def test_opi_two_sweeps_hand_trajectory():
+    """OPI(2) on the two-state example, every step solved by hand
+    (tests/golden/two_state_opi.json): the outer step, the number of
+    applications of T^pi, the iterate and the greedy policy at each stop."""
+    mdp, _ = two_state()
+    d = json.load(open(os.path.join(GOLD, "two_state_opi.json")))
+    for row in d["stops"]:
+        V, pi, outer, total = O.opi(mdp, d["sweeps"], tol=row["tol"], V0=np.array(d["V0"]))
+        assert (outer, total) == (row["outer"], row["total_sweeps"]), row
+        np.testing.assert_array_equal(V, row["V"])
+        assert pi.tolist() == row["pi"]
+        _, _, res = O.bellman(mdp, V)
+        assert res == row["res"]
+    # exact PI from the same start: the W -> infinity limit of OPI
+    seq = []
+    O.policy_iteration(mdp, V0=np.array(d["V0"]), trace=seq)
+    assert [p.tolist() for p in seq] == d["pi_sequence_PI"]
+
+
+@pytest.mark.parametrize("case", ["c1-0", "c1-1", "c1-2", "u200"])
+def test_opi_many_sweeps_is_policy_iteration(case):
+    """Sec. 2.1: as the number W of T^pi applications per step grows, OPI
+    becomes PI.  With gamma^W below the rounding unit, (T^pi)^W V equals
+    V^pi to rounding, so OPI's greedy policies are exact PI's (LU
+    evaluation) and it stops one step after evaluating the optimal policy."""
+    if case.startswith("c1"):
+        mdp = synth.config("c1", int(case[-1]))
+    else:
+        mdp = synth.sparse_uniform(200, 4, 6, 0.99, seed=31)
+    W = int(np.ceil(np.log(1e-20) / np.log(mdp.gamma)))
+    seq_pi, seq_opi = [], []
+    Vp, pip, it = O.policy_iteration(mdp, trace=seq_pi)
+    Vo, pio, outer, total = O.opi(mdp, W, tol=1e-10 * np.max(np.abs(Vp)), trace=seq_opi)
+    assert outer == it and total == it * W
+    for a, b in zip(seq_pi, seq_opi[:it]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(seq_opi[it], pip)
+    np.testing.assert_allclose(Vo, Vp, rtol=1e-12)
+
+
 def test_certificate_bounds_error(small):
     Vs, _, _ = O.policy_iteration(small)
     rng = np.random.default_rng(12)
