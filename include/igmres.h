@@ -96,6 +96,22 @@ typedef struct {
                               empty); the Bellman operator, greedy policies
                               and every solver minimise over A(s) only, and
                               policies passed in must lie in A(s).            */
+  int32_t refine;          /* 0: one stored copy of P, in `store`.  1
+                              (residual-corrected evaluation; needs store ==
+                              IG_BF16 and val_type FP64 or FP32): the P^pi
+                              products inside GMRES (and the preconditioner
+                              steps) read P^pi rounded to BF16, while every
+                              Bellman pass, every true residual of the
+                              stopping tests and restarts, the policy gather
+                              and the value-iteration sweeps read an FP32
+                              copy of P.  The outer iteration then converges
+                              to the optimum of the FP32-stored MDP; an
+                              explicit residual that misses the inexact rule
+                              restarts the GMRES cycle from that residual
+                              (iterative refinement of the BF16 solve).
+                              Stream engine only (igmres_pi_solve with
+                              engine 0 takes it; engine 2 and serving refuse
+                              such a handle).                                 */
 } ig_mdp_desc;
 
 /* Solver parameters.  Algorithm 2's inputs are V0 (the V argument), alpha,
@@ -119,8 +135,10 @@ typedef struct {
   int32_t engine;      /* igmres_pi_solve: 0 auto, 1 one kernel launch per
                           step (any size, dense or sparse), 2 a single
                           persistent launch for the whole solve (sparse,
-                          up to 256*32 slices of 64 states); auto picks 2
-                          when it applies.  Engine 2's grid barriers wait
+                          up to 256*32 slices of 64 states, restart <= 64,
+                          no preconditioner); auto picks 2 when all of
+                          these hold and 1 otherwise.  Engine 2's grid
+                          barriers wait
                           a bounded number of polls (environment variable
                           IG_SPIN_LIMIT overrides, for tests of the error
                           path); a wait that runs out ends the solve with
@@ -205,6 +223,11 @@ typedef struct {
   int32_t persistent_ok;  /* igmres_pi_solve with engine 0 uses one persistent
                              launch per solve on this handle                */
   int32_t persistent_blocks;
+  int32_t refine;         /* 1: BF16 products inside GMRES beside an FP32
+                             copy for every other pass (store and p_bytes
+                             then describe the FP32 copy; inner_p_bytes the
+                             BF16 one)                                       */
+  int64_t inner_p_bytes;  /* device bytes of the BF16 copy (0 without refine)*/
 } ig_mdp_info;
 ig_status mdp_get_info(ig_mdp_t mdp, ig_mdp_info* info);
 

@@ -151,7 +151,34 @@ void launch_fill_in(const ConvArgs& c, ig_dtype store, hipStream_t s) {
   }
 }
 
+// BF16 copy of FP32 values (the rounding of the conversion above): four
+// values per thread and step, grid-stride
+__global__ __launch_bounds__(kBlock) void k_round_bf16(const float* __restrict__ src,
+                                                       uint16_t* __restrict__ dst, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock * 4;
+  for (int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 4; e < count; e += stride) {
+    if (e + 4 <= count) {
+      const float4 v = *reinterpret_cast<const float4*>(src + e);
+      ushort4 o;
+      o.x = bf16_bits(v.x);
+      o.y = bf16_bits(v.y);
+      o.z = bf16_bits(v.z);
+      o.w = bf16_bits(v.w);
+      *reinterpret_cast<ushort4*>(dst + e) = o;
+    } else {
+      for (int64_t k = e; k < count; ++k) dst[k] = bf16_bits(src[k]);
+    }
+  }
+}
+
 }  // namespace
+
+void launch_round_bf16(const float* src, void* dst, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t blocks = std::min<int64_t>((count + 4 * kBlock - 1) / (4 * kBlock), 4096);
+  hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)blocks), dim3(kBlock), 0, s, src, (uint16_t*)dst,
+                     count);
+}
 
 void launch_fill_sell(const ConvArgs& c, ig_dtype val_type, ig_dtype store, hipStream_t s) {
   switch (val_type) {

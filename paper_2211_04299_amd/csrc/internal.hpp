@@ -91,6 +91,16 @@ struct Mdp {
   // dense input: P[s][a][s'] row-major
   void* P = nullptr;
 
+  // residual-corrected evaluation: store/vb/val/pval/P above are the FP32
+  // copy that the Bellman passes, residuals, gathers and sweeps read; the
+  // P^pi products inside GMRES read these BF16 arrays (sparse: the compact
+  // P^pi rounded after each Bellman pass or gather; dense: all of P)
+  bool refine = false;
+  ig_dtype in_store = IG_FP64;
+  int in_vb = 8;
+  void* in_pval = nullptr;
+  void* in_P = nullptr;
+
   uint8_t* adm = nullptr;  // [m][n] admissibility (null: all actions admissible)
   double* cost = nullptr;  // [m][n] (transposed; 0 for excluded pairs)
   double* cpi = nullptr;   // g^pi
@@ -128,6 +138,25 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// For the P^pi products inside GMRES: with refine set, the handle's storage
+// fields name the BF16 copy for the lifetime of this object.
+struct InnerView {
+  Mdp& d;
+  explicit InnerView(Mdp& d_) : d(d_) { flip(); }
+  ~InnerView() { flip(); }
+  void flip() {
+    if (!d.refine) return;
+    std::swap(d.store, d.in_store);
+    std::swap(d.vb, d.in_vb);
+    std::swap(d.pval, d.in_pval);
+    std::swap(d.P, d.in_P);
+  }
+};
+
+// FP32 -> BF16 (round to nearest even) of `count` values, for the BF16 copy
+// of the refine mode
+void launch_round_bf16(const float* src, void* dst, int64_t count, hipStream_t s);
+
 ig_status ensure_workspace(Mdp& d, int W, bool fp32);
 ig_status sync_status(Mdp& d, hipStream_t s);
 
@@ -161,6 +190,9 @@ void launch_vi_sweep_dense(Mdp& d, const int32_t* pi, const double* Vin, double*
 void launch_gather_policy_dense(Mdp& d, const int32_t* pi, hipStream_t s);
 
 // ---- persistent single-launch solver (sparse, up to kPMaxBlocks*kPMaxSpb slices)
+// Longest restart cycle the persistent engine holds (its Givens state lives
+// in LDS); longer cycles run on the stream engine.
+constexpr int kPersistMaxRestart = 64;
 // Returns IG_E_TOO_LARGE (without side effects) when the shape does not fit
 // the persistent engine; the caller then uses the stream engine.
 ig_status persistent_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stats& st,

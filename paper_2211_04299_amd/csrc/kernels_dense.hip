@@ -609,6 +609,7 @@ void launch_bellman_dense(Mdp& d, const double* V, double* TV, double* Phi, int3
 void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* eta,
                          void* y, hipStream_t s) {
   ProfScope p(d, KC_JAPPLY, s);
+  InnerView iv(d);
   by_store(d, [&](auto t) {
     using VT = decltype(t);
     auto go = [&](auto kern, auto xt, int sg) {
@@ -644,6 +645,7 @@ void launch_japply_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, co
 void launch_pstep_dense(Mdp& d, bool fp32, const int32_t* pi, const void* x, const double* sx,
                         const void* z, const double* sz, void* y, hipStream_t s) {
   ProfScope p(d, KC_JAPPLY, s);
+  InnerView iv(d);
   by_store(d, [&](auto t) {
     using VT = decltype(t);
     if (fp32)

@@ -41,7 +41,7 @@ constexpr int kPWaves = kPB / kWave;
 constexpr int kPMaxBlocks = 256;
 constexpr int kPMaxSpb = 32;         // slices per block
 constexpr int kPMaxOwn = kPMaxSpb * kSlice;
-constexpr int kPMaxW = 64;           // restart cap of this engine (LDS Givens state)
+constexpr int kPMaxW = kPersistMaxRestart;  // restart cap of this engine (LDS Givens state)
 constexpr int kPStride = kPMaxW + 8; // doubles per block row of partials
 constexpr long kSpinLimit = 1L << 23;  // polls per barrier wait (IG_SPIN_LIMIT overrides)
 
@@ -903,7 +903,7 @@ int persistent_grid(const Mdp& d, int requested) {
 }
 
 bool persistent_fits(const Mdp& d) {
-  if (d.fmt != IG_FMT_CSR || d.num_cu <= 0) return false;
+  if (d.fmt != IG_FMT_CSR || d.num_cu <= 0 || d.refine) return false;
   int spb = 0;
   persistent_blocks(d, &spb);
   return spb <= kPMaxSpb && d.n >= 1;

@@ -386,17 +386,20 @@ void launch_bellman_sparse(Mdp& d, const double* V, double* TV, double* Phi, int
     dispatch_vt_g<RunBellman>(d, d.G_bell, d, V, TV, Phi, pi, pi_old, tie_abs, compact, s);
   }
   launch_finalize(d, FIN_BELLMAN, grid_for(d, d.G_bell), s);
+  if (compact && d.refine) launch_round_bf16((const float*)d.pval, d.in_pval, d.stored_pi, s);
 }
 
 void launch_japply_sparse(Mdp& d, bool fp32, const void* x, const double* eta, void* y,
                           hipStream_t s) {
   ProfScope p(d, KC_JAPPLY, s);
+  InnerView iv(d);
   dispatch_vt_g<RunJapply>(d, d.G_jap, d, fp32, x, eta, y, s);
 }
 
 void launch_pstep_sparse(Mdp& d, bool fp32, const void* x, const double* sx, const void* z,
                          const double* sz, void* y, hipStream_t s) {
   ProfScope p(d, KC_JAPPLY, s);
+  InnerView iv(d);
   dispatch_vt_g<RunPstep>(d, d.G_jap, d, fp32, x, sx, z, sz, y, s);
 }
 
@@ -422,6 +425,7 @@ void launch_gather_policy_sparse(Mdp& d, const int32_t* pi, hipStream_t s) {
     dispatch_vt_g<RunGather>(d, d.G_jap, d, pi, s);
   }
   launch_finalize(d, FIN_GATHER, grid_for(d, d.G_jap), s);
+  if (d.refine) launch_round_bf16((const float*)d.pval, d.in_pval, d.stored_pi, s);
 }
 
 }  // namespace ig

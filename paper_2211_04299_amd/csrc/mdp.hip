@@ -305,6 +305,7 @@ void free_all(Mdp* d) {
     if (p && dev) (void)hipFree(p);
   };
   F(d->col); F(d->val); F(d->off); F(d->width); F(d->mcnt); F(d->offp); F(d->pcol); F(d->pval);
+  F(d->in_pval); F(d->in_P);
   F(d->adm);
   F(d->P); F(d->cost); F(d->cpi); F(d->st); F(d->gs); F(d->part); F(d->pctl);
   F(d->ws.Q); F(d->ws.wA); F(d->ws.wB); F(d->ws.Vb); F(d->ws.r); F(d->ws.t); F(d->ws.pi);
@@ -392,6 +393,9 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     if (t != IG_FP64 && t != IG_FP32 && t != IG_BF16) return fail(IG_E_INVALID, "bad dtype");
   if (dtype_bytes(desc->store) > dtype_bytes(desc->val_type))
     return fail(IG_E_INVALID, "storage type wider than the input type");
+  if (desc->refine != 0 && desc->refine != 1) return fail(IG_E_INVALID, "refine must be 0 or 1");
+  if (desc->refine && (desc->store != IG_BF16 || desc->val_type == IG_BF16))
+    return fail(IG_E_INVALID, "refine needs store IG_BF16 and FP64 or FP32 input values");
   if (!desc->val || !desc->cost) return fail(IG_E_INVALID, "val and cost are required");
   if (desc->fmt == IG_FMT_CSR && (!desc->row_ptr || !desc->col))
     return fail(IG_E_INVALID, "CSR needs row_ptr and col");
@@ -400,8 +404,12 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
   d->m = m;
   d->gamma = desc->gamma;
   d->fmt = desc->fmt;
-  d->store = desc->store;
-  d->vb = dtype_bytes(desc->store);
+  // refine: the arrays built below hold the FP32 copy; the BF16 one follows
+  d->refine = desc->refine != 0;
+  d->store = d->refine ? IG_FP32 : desc->store;
+  d->vb = dtype_bytes(d->store);
+  d->in_store = desc->store;
+  d->in_vb = dtype_bytes(desc->store);
   const int64_t R = n * (int64_t)m;
   const bool ondev = desc->inputs_on_device != 0;
   ig_status st;
@@ -697,6 +705,10 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     }
     if (ig_status e = dzero(d, d->pcol, (size_t)totp * 4)) return e;
     if (ig_status e = dzero(d, d->pval, (size_t)totp * d->vb)) return e;
+    if (d->refine) {  // BF16 compact P^pi, rounded from the FP32 one per policy
+      if (dmalloc(&d->in_pval, (size_t)totp * d->in_vb)) return IG_E_NOMEM;
+      if (ig_status e = dzero(d, d->in_pval, (size_t)totp * d->in_vb)) return e;
+    }
 
     // lanes per state: enough lanes in flight to cover latency on 256 CUs
     const int64_t target = (int64_t)1 << 18;
@@ -744,6 +756,12 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     d->maxK = (int)n;
     if (dmalloc(&d->P, (size_t)total * d->vb)) return IG_E_NOMEM;
     if (ig_status e = upload(d, d->P, sval, (size_t)total * d->vb)) return e;
+    if (d->refine) {  // BF16 copy of all of P, rounded from the FP32 copy
+      if (dmalloc(&d->in_P, (size_t)total * d->in_vb)) return IG_E_NOMEM;
+      if (!d->region) IG_HIP(hipDeviceSynchronize());
+      launch_round_bf16((const float*)d->P, d->in_P, total, d->stream);
+      IG_HIP(hipGetLastError());
+    }
   }
 
   if (dmalloc(&d->cost, (size_t)R * 8) || dmalloc(&d->cpi, (size_t)n * 8) ||
@@ -860,7 +878,8 @@ ig_status region_alloc(Mdp& d, size_t bytes, void** p) {
 ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size_t* bytes) {
   if (!desc || !bytes || desc->n < 1 || desc->m < 1) return fail(IG_E_INVALID, "bad description");
   const int64_t n = desc->n, R = n * (int64_t)desc->m;
-  const size_t vb = dtype_bytes(desc->store);
+  // refine: an FP32 copy of P, plus BF16 P^pi (sparse) or BF16 P (dense)
+  const size_t vb = desc->refine ? 4 : dtype_bytes(desc->store);
   size_t b = 0, staging = 0;
   if (desc->fmt == IG_FMT_CSR) {
     if (desc->inputs_on_device) return fail(IG_E_INVALID, "footprint needs host CSR arrays");
@@ -884,6 +903,7 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
     }
     b += round256(tot * 4) + round256(tot * vb) + 2 * round256(ns * 8) + 2 * round256(ns * 4) +
          round256(totp * 4) + round256(totp * vb);
+    if (desc->refine) b += round256(totp * 2);
     // raw CSR staging of the device conversion: taken from the top of a
     // region after the sliced-ELL arrays (and the mask), dead once the
     // conversion is done, so the later allocations may reuse its bytes
@@ -892,6 +912,7 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
               round256(5 * sizeof(unsigned long long));
   } else {
     b += round256((size_t)R * n * vb);
+    if (desc->refine) b += round256((size_t)R * n * 2);
   }
   if (desc->admissible) b += round256(R);
   const size_t at_staging = b + staging;
@@ -977,6 +998,9 @@ ig_status mdp_get_info(ig_mdp_t mdp, ig_mdp_info* info) {
   info->gamma = d.gamma;
   info->persistent_ok = (d.coop && ig::persistent_fits(d)) ? 1 : 0;
   info->persistent_blocks = info->persistent_ok ? ig::persistent_grid(d) : 0;
+  info->refine = d.refine ? 1 : 0;
+  info->inner_p_bytes =
+      !d.refine ? 0 : (d.fmt == IG_FMT_CSR ? d.stored_pi : d.stored) * (int64_t)d.in_vb;
   return IG_OK;
 }
 

@@ -496,13 +496,14 @@ ig_status srv_submit(ig_server_t srv, const ig_mdp_desc* desc, const double* V0,
   Server& S = srv->S;
   if (desc->fmt != IG_FMT_CSR) return fail(IG_E_INVALID, "serving takes CSR MDPs");
   if (desc->inputs_on_device) return fail(IG_E_INVALID, "serving takes host arrays");
+  if (desc->refine) return fail(IG_E_INVALID, "serving runs the persistent engine: refine must be 0");
   if (desc->n < 1 || desc->m < 1 || !desc->row_ptr || !desc->col || !desc->val || !desc->cost)
     return fail(IG_E_INVALID, "malformed MDP description");
   if (desc->n > S.cfg.max_states) return fail(IG_E_TOO_LARGE, "n exceeds the server's max_states");
   const ig_params& p = *params;
   if (!(p.alpha > 0.0 && p.alpha < 1.0)) return fail(IG_E_INVALID, "alpha must be in (0,1)");
   if (p.restart < 1) return fail(IG_E_INVALID, "restart must be >= 1");
-  if (p.restart > 64) return fail(IG_E_TOO_LARGE, "serving takes restart <= 64");
+  if (p.restart > kPersistMaxRestart) return fail(IG_E_TOO_LARGE, "serving takes restart <= 64");
   if (p.max_outer < 1 || p.max_inner < 1) return fail(IG_E_INVALID, "iteration caps must be >= 1");
   if (!(p.tol > 0.0)) return fail(IG_E_INVALID, "tol must be > 0");
   if (p.mode != IG_MODE_FP64 && p.mode != IG_MODE_MIXED) return fail(IG_E_INVALID, "bad mode");

@@ -65,9 +65,15 @@ void k_gather(Mdp& d, const int32_t* pi, hipStream_t s) {
 struct Bytes {
   const Mdp& d;
   double entry() const { return d.vb + (d.fmt == IG_FMT_CSR ? 4.0 : 0.0); }
+  // entries of the products inside GMRES (the BF16 copy in refine mode)
+  double entry_in() const { return d.in_vb + (d.fmt == IG_FMT_CSR ? 4.0 : 0.0); }
   double nnz_pi() const { return (double)d.nnz / d.m; }
-  double bellman() const { return d.nnz * entry() + d.n * (double)d.m * 8 + d.n * (8.0 + 8 + 4); }
-  double japply(bool fp32) const { return nnz_pi() * entry() + d.n * (fp32 ? 4.0 : 8.0) * 2; }
+  // refine mode, sparse: the compact P^pi is rounded to BF16 after the pass
+  double bellman() const {
+    return d.nnz * entry() + d.n * (double)d.m * 8 + d.n * (8.0 + 8 + 4) +
+           (d.refine && d.fmt == IG_FMT_CSR ? nnz_pi() * (d.vb + d.in_vb) : 0.0);
+  }
+  double japply(bool fp32) const { return nnz_pi() * entry_in() + d.n * (fp32 ? 4.0 : 8.0) * 2; }
   // Orthogonalisation of column c.  Fused form: pass A reads Q_0..Q_{c-1},
   // w1 and y and writes Q_c (c = 0: reads Q_0 and y); pass B reads
   // Q_0..Q_c and y and writes w1.  Separate form: formation (c columns + w1
@@ -136,6 +142,25 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
   void* w1 = ws.wB;  // once-orthogonalised Arnoldi vector
   const double* eta_dev = &d.st->eta;
 
+  // a new cycle from the true residual at the current iterate (in ws.r, its
+  // squared 2-norm in the status); `stop` when the last cycle lowered the
+  // residual 2-norm by less than the stagnation factor
+  bool stop = false;
+  auto restart = [&]() -> ig_status {
+    const double nb = std::sqrt(d.hst->res_l2sq);
+    if (nb > (1.0 - kStagnation) * cycle_beta) {
+      out.stagnated = true;
+      stop = true;
+      return IG_OK;
+    }
+    cycle_beta = nb;
+    ++out.restarts;
+    IG_HIP(hipMemcpyAsync(ws.Vb, V, (size_t)d.n * 8, hipMemcpyDeviceToDevice, s));
+    launch_form_q0(d, fp32, ws.r, &d.st->res_l2sq, s);
+    out.bytes += d.n * (8.0 + xb + 16);
+    return IG_OK;
+  };
+
   // V = Vb + Q_{0..cnt-1} y and its true residual (FP64)
   auto explicit_residual = [&](int cnt) -> ig_status {
     if (precond == 0) {
@@ -174,6 +199,16 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
         out.met = true;
         return IG_OK;
       }
+      if (d.refine) {
+        // refine mode: the BF16 system's residual meets the rule, the FP32
+        // one does not; the next cycle solves for the correction from the
+        // true residual (column c is dropped)
+        --out.steps;
+        if (ig_status e = restart()) return e;
+        if (stop) return IG_OK;
+        c = 0;
+        continue;
+      }
     }
     if (eta == 0.0) {  // ||q||_2 = 0: the least-squares solution is exact; leave the loop
       ++out.breakdowns;
@@ -190,17 +225,11 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
       }
       if (out.steps >= max_inner) return IG_OK;
     }
-    if (c + 1 == W) {  // restart from the residual at the current iterate
-      const double nb = std::sqrt(d.hst->res_l2sq);
-      if (nb > (1.0 - kStagnation) * cycle_beta) {
-        out.stagnated = true;
-        return IG_OK;
-      }
-      cycle_beta = nb;
-      ++out.restarts;
-      IG_HIP(hipMemcpyAsync(ws.Vb, V, (size_t)d.n * 8, hipMemcpyDeviceToDevice, s));
-      launch_form_q0(d, fp32, ws.r, &d.st->res_l2sq, s);
-      out.bytes += d.n * (8.0 + xb + 16);
+    // restart from the residual at the current iterate at the end of a
+    // cycle, and in refine mode after any explicit residual that missed
+    if (c + 1 == W || (d.refine && rho <= thr)) {
+      if (ig_status e = restart()) return e;
+      if (stop) return IG_OK;
       c = 0;
       continue;
     }
@@ -220,7 +249,8 @@ ig_status check_params(const Mdp& d, const ig_params* p, bool need_alpha) {
   if (p->precond < 0 || p->precond > 16) return fail(IG_E_INVALID, "precond must be in 0..16");
   if (p->precond > 0 && p->engine == 2)
     return fail(IG_E_INVALID, "the persistent engine has no preconditioner (use engine 0 or 1)");
-  (void)d;
+  if (d.refine && p->engine == 2)
+    return fail(IG_E_INVALID, "the persistent engine does not take refine-mode handles (use engine 0 or 1)");
   return IG_OK;
 }
 
@@ -261,7 +291,8 @@ ig_status run_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, ig_stat
                      hipStream_t s) {
   const bool fp32 = p.mode == IG_MODE_MIXED;
   if (p.engine < 0 || p.engine > 2) return fail(IG_E_INVALID, "engine must be 0, 1 or 2");
-  if (p.engine == 2 || (p.engine == 0 && p.precond == 0 && d.coop && persistent_fits(d)))
+  if (p.engine == 2 || (p.engine == 0 && p.precond == 0 && p.restart <= kPersistMaxRestart &&
+                        d.coop && persistent_fits(d)))
     return persistent_igmres(d, V, pi, p, st, s);
   if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
   // polish: pi_{k-1}, kept in the spare vector, and the Bellman pass counts

@@ -45,7 +45,7 @@ class MdpDesc(C.Structure):
                 ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
                 ("val_type", C.c_int), ("cost", C.c_void_p), ("store", C.c_int),
                 ("inputs_on_device", C.c_int32), ("validate", C.c_int32),
-                ("admissible", C.c_void_p)]
+                ("admissible", C.c_void_p), ("refine", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -72,7 +72,7 @@ class MdpInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("max_width", C.c_int32), ("nnz", C.c_int64),
                 ("stored_entries", C.c_int64), ("p_bytes", C.c_int64), ("store", C.c_int),
                 ("fmt", C.c_int), ("gamma", C.c_double), ("persistent_ok", C.c_int32),
-                ("persistent_blocks", C.c_int32)]
+                ("persistent_blocks", C.c_int32), ("refine", C.c_int32), ("inner_p_bytes", C.c_int64)]
 
 
 class ServerConfig(C.Structure):
@@ -235,10 +235,11 @@ class Mdp:
         return {PROFILE_CLASS_NAMES[k]: (ms[k], cnt[k]) for k in range(IG_PROFILE_CLASSES)}
 
 
-def _desc(mdp, store, validate):
+def _desc(mdp, store, validate, refine=False):
     """MdpDesc for a synth.MDP-like object with host arrays, plus the arrays
     it points into (to be kept alive by the caller)."""
     d = MdpDesc()
+    d.refine = int(refine)
     d.n, d.m, d.gamma = mdp.n, mdp.m, float(mdp.gamma)
     keep = []
     if mdp.fmt == "csr":
@@ -271,7 +272,7 @@ def _desc(mdp, store, validate):
     return d, keep
 
 
-def _desc_device(mdp, store, validate):
+def _desc_device(mdp, store, validate, refine=False):
     """Description of a CSR MDP whose arrays are device tensors (row_ptr
     int64, col int32, val float64/float32/int16-or-uint16 bf16 patterns,
     cost float64, adm uint8/bool or None)."""
@@ -279,6 +280,7 @@ def _desc_device(mdp, store, validate):
     if mdp.fmt != "csr":
         raise ValueError("device inputs are taken for CSR MDPs")
     d = MdpDesc()
+    d.refine = int(refine)
     d.n, d.m, d.gamma = mdp.n, mdp.m, float(mdp.gamma)
     d.fmt = IG_FMT_CSR
     vt = {torch.float64: IG_FP64, torch.float32: IG_FP32, torch.int16: IG_BF16,
@@ -300,12 +302,14 @@ def _desc_device(mdp, store, validate):
 
 
 def mdp_create(mdp, store: str = "fp64", validate: bool = True, stream=None,
-               inputs_on_device: bool = False) -> Mdp:
+               inputs_on_device: bool = False, refine: bool = False) -> Mdp:
     """Create a device MDP from a synth.MDP-like object with host arrays
     (fmt "csr": row_ptr/col/val; "dense": P).  `mdp.val` / `mdp.P` may be
     float64, float32 or uint16 (bf16 bit patterns).  inputs_on_device: the
-    CSR arrays, costs and mask are device tensors instead."""
-    d, keep = (_desc_device if inputs_on_device else _desc)(mdp, store, validate)
+    CSR arrays, costs and mask are device tensors instead.  refine (with
+    store "bf16"): BF16 products inside GMRES beside an FP32 copy for every
+    other pass (ig_mdp_desc.refine)."""
+    d, keep = (_desc_device if inputs_on_device else _desc)(mdp, store, validate, refine)
     h = C.c_void_p()
     _check(_lib.mdp_create(C.byref(d), stream, C.byref(h)), "mdp_create")
     del keep

@@ -32,10 +32,25 @@ def tol_par(mdp, vstar_inf):
 
 
 def assert_policy_match(mdp, Vstar, pi_star, pi, gap_min=1e-9):
-    gaps = O.action_gaps(mdp, Vstar)
+    """pi equals the optimal policy wherever the action gap at V* exceeds
+    gap_min; at the other states (near-ties, where several policies are
+    optimal) the chosen action must be admissible and gap_min-optimal at V*:
+    Q*(s, pi(s)) - min_a Q*(s, a) <= gap_min (up to rounding of Q*).  A
+    policy greedy for V with 2 gamma ||V - V*||_inf <= gap_min meets both."""
+    Q = O.q_values(mdp, Vstar)
+    srt = np.sort(Q, axis=1)
+    gaps = srt[:, 1] - srt[:, 0] if mdp.m > 1 else np.full(mdp.n, np.inf)
     sel = gaps > gap_min
     bad = np.nonzero(pi[sel] != pi_star[sel])[0]
     assert bad.size == 0, f"{bad.size} policy mismatches where the action gap > {gap_min}"
+    pi = np.asarray(pi, np.int64)
+    assert np.all((pi >= 0) & (pi < mdp.m)), "policy entry out of range"
+    q_pi = Q[np.arange(mdp.n), pi]
+    assert np.all(np.isfinite(q_pi)), "policy picks an action outside A(s)"
+    slack = gap_min + 1e-13 * max(1.0, float(np.max(np.abs(srt[:, 0]))))
+    sub = q_pi - srt[:, 0]
+    worst = float(np.max(sub)) if sub.size else 0.0
+    assert worst <= slack, f"an action {worst:.3e} above the optimum at a near-tie state"
 
 
 def rel_err(V, Vstar):

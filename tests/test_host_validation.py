@@ -127,3 +127,12 @@ def test_excluded_rows_and_costs_are_ignored():
         I.mdp_create(m).close()
     except I.IgError as e:
         assert e.status != I.IG_E_INVALID, str(e)
+
+
+def test_refine_needs_bf16_store_and_wider_input():
+    """The refine mode keeps an FP32 copy beside BF16 products: it takes
+    store bf16 and FP64 or FP32 input values only."""
+    m = base()
+    assert "refine" in expect_invalid(m, store="fp32", refine=True)
+    m16 = m.with_values(val=synth.round_values(m.val, "bf16"))
+    assert "refine" in expect_invalid(m16, store="bf16", refine=True)
