@@ -1,9 +1,13 @@
 """Benchmark: inexact GMRES policy iteration (Algorithm 2) solved to
-||T V - V||_inf <= 1e-8 from V0 = 0 on the paper-scale sparse workload
-(n = 10000 states, m = 8 actions, k = 20 successors per (s, a) drawn without
-replacement, Dirichlet(1) probabilities, c ~ U[0,1], gamma = 0.99, GMRES
-restart 30, FP64 values and int32 columns).  One step = one full solve with
-the MDP already resident in HBM.
+||T V - V||_inf <= 1e-8 from V0 = 0 on the largest single-GPU workload (c4:
+n = 4e6 states, m = 8 actions, k = 16 successors per (s, a), 90% in the band
+|s' - s| <= 64 and 10% uniform, Dirichlet(0.5) probabilities, c ~ U[0,1],
+gamma = 0.995, GMRES restart 40; P stored in FP32 with int32 columns, FP32
+Krylov basis and products, FP64 Bellman residual, solution update and
+Hessenberg/Givens solve).  One step = one full solve with the MDP already
+resident in HBM.  --workload picks another (c2: the paper-scale n = 1e4,
+m = 8, k = 20 FP64 workload; c1; c3 dense; c3-bf16; c3-bf16r with the FP32
+refinement copy).
 
 Prints one JSON line.  Extra keys: "roofline" for the dominant kernel (HIP
 events around its launches during the timed steps; algorithmic bytes per
@@ -25,7 +29,12 @@ the published peak.
 Also reported: per-solve device time p50/p90, the upload (mdp_create)
 time, and under "compare" the same workload by exact-evaluation PI and by
 OPI with 20 sweeps (FP64 workloads) or with FP64 storage and arithmetic
-(mixed workloads), each timed from V0 = 0 to the same tolerance.
+(mixed workloads), each timed from V0 = 0 to the same tolerance.  Under
+"extra" the other single-GPU workloads are timed in the same run (c2 with
+its PI and OPI comparisons; c3 with FP32, BF16 and BF16 + FP32 refinement
+storage against FP64), and "cpu_baseline" carries the oracle's times on one
+host core and on all of them, with the host's CPU model and core count, plus
+the oracle's PI with LU evaluation, value iteration and Algorithm 2 on c2.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c4|c3|c3-bf16|c5]
                     [--serve-requests R] [--no-serving] [--no-compare]
@@ -55,8 +64,13 @@ WORKLOADS = {
                desc="dense n=10000 m=4 gamma=0.99 W=30 FP32-stored P, mixed, tol 1e-8, V0=0"),
     "c3-bf16": dict(cfg="c3", store="bf16", mode="mixed",
                     desc="dense n=10000 m=4 gamma=0.99 W=30 BF16-stored P, mixed, tol 1e-8, V0=0"),
+    "c3-bf16r": dict(cfg="c3", store="bf16", mode="mixed", refine=True,
+                     desc="dense n=10000 m=4 gamma=0.99 W=30 BF16 P inside GMRES, FP32 copy for "
+                          "Bellman passes and residuals, mixed, tol 1e-8, V0=0"),
     "c4": dict(cfg="c4", store="fp32", mode="mixed",
-               desc="banded sparse n=4e6 m=8 k=16 gamma=0.995 W=40 FP32 P, mixed, tol 1e-8, V0=0"),
+               desc="banded sparse n=4e6 m=8 k=16 (90% within +-64, 10% uniform) Dirichlet(0.5) "
+                    "gamma=0.995 W=40; P in FP32 (int32 cols), FP32 basis and P^pi products, "
+                    "FP64 Bellman residual, update and Givens; tol 1e-8, V0=0"),
 }
 
 
@@ -83,14 +97,15 @@ def kernel_group(dom, fmt):
 
 def per_launch_bytes(info, cls, fp32):
     """Algorithmic bytes one launch of a kernel class must move."""
-    entry = (8 if info.store == 0 else 4 if info.store == 1 else 2) + (4 if info.fmt == 0 else 0)
+    idx = 4 if info.fmt == 0 else 0
+    entry = (8 if info.store == 0 else 4 if info.store == 1 else 2) + idx
     n, m = info.n, info.m
     xb = 4 if fp32 else 8
     nnz_pi = info.nnz / m
     if cls == "bellman":  # P (all actions), g, V; Phi, pi and g^pi out
         return info.nnz * entry + n * m * 8 + n * 8 + n * (8 + 4 + 8)
-    if cls == "japply":   # P^pi, x in, y out, basis column out
-        return nnz_pi * entry + n * xb * 3
+    if cls == "japply":   # P^pi (the BF16 copy in refine mode), x in, y out
+        return nnz_pi * ((2 + idx) if getattr(info, "refine", 0) else entry) + n * xb * 2
     if cls == "residual":
         return nnz_pi * entry + n * 8 * 3
     return None  # classes whose bytes depend on the step (persistent, Gram-Schmidt)
@@ -168,23 +183,25 @@ def comparisons(igmres, torch, mdp, wl, restart, igmres_ms, runs, V_main=None):
 CPU_FULL_NNZ = 50_000_000  # above this, the oracle is timed on a reduced instance
 
 
-def cpu_baseline(mdp, restart, synth=None, wl_cfg=None, seed=0, budget_s=12.0):
-    """The oracle's literal Algorithm 2 on one host thread for about
-    budget_s seconds.  Workloads with more than CPU_FULL_NNZ entries are
-    sampled by solves of the same recipe with a tenth of the states,
-    scaled to the full size by the entry count (the oracle's work per
-    iteration is linear in it)."""
-    from threadpoolctl import threadpool_limits
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "nproc": cores, "logical_cpus": os.cpu_count()}
 
-    from oracle import mdp_oracle as O
-    scale, what = 1.0, "the same workload"
-    if synth is not None and mdp.fmt == "csr" and mdp.nnz > CPU_FULL_NNZ:
-        small = synth.config(wl_cfg, seed=seed, n=max(1000, mdp.n // 10))
-        scale = mdp.nnz / small.nnz
-        what = (f"the same recipe at n={small.n} ({small.nnz} entries), scaled by the entry "
-                f"ratio {scale:.1f} to the full workload")
-        mdp = small
-    with threadpool_limits(1):
+
+def _oracle_rate(O, mdp, restart, threads, budget_s):
+    """Solves per second of the oracle's Algorithm 2 on `threads` threads."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(threads):
         t0 = time.perf_counter()
         count = 0
         while True:
@@ -193,9 +210,93 @@ def cpu_baseline(mdp, restart, synth=None, wl_cfg=None, seed=0, budget_s=12.0):
             el = time.perf_counter() - t0
             if el >= budget_s or count >= 1000:
                 break
-    return {"value": count / el / scale, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{count} full solves of {what} by the oracle's literal Algorithm 2 "
-                      f"(NumPy/SciPy FP64, 1 thread) in {el:.1f} s"}
+    return count, el
+
+
+def cpu_baseline(mdp, restart, synth=None, wl_cfg=None, seed=0, budget_s=8.0, c2_legs=True):
+    """The oracle's literal Algorithm 2 on the host for about budget_s seconds
+    on all cores (the reported value) and again on one core.  Workloads with
+    more than CPU_FULL_NNZ entries are sampled by solves of the same recipe
+    with a tenth of the states, scaled to the full size by the entry count
+    (the oracle's work per iteration is linear in it).  c2_legs: the oracle's
+    PI with LU evaluation, value iteration and Algorithm 2 on c2, once each,
+    on all cores."""
+    from oracle import mdp_oracle as O
+    host = host_cpu()
+    scale, what = 1.0, "the same workload"
+    if synth is not None and mdp.fmt == "csr" and mdp.nnz > CPU_FULL_NNZ:
+        small = synth.config(wl_cfg, seed=seed, n=max(1000, mdp.n // 10))
+        scale = mdp.nnz / small.nnz
+        what = (f"the same recipe at n={small.n} ({small.nnz} entries), scaled by the entry "
+                f"ratio {scale:.1f} to the full workload")
+        mdp = small
+    allc = host["nproc"]
+    n_all, t_all = _oracle_rate(O, mdp, restart, allc, budget_s)
+    n_one, t_one = _oracle_rate(O, mdp, restart, 1, budget_s)
+    out = {"value": n_all / t_all / scale, "unit": "solves/s", "cores": allc, "kind": "oracle",
+           "sample": f"{n_all} full solves of {what} by the oracle's literal Algorithm 2 "
+                     f"(NumPy/SciPy FP64, BLAS on {allc} threads) in {t_all:.1f} s",
+           "single_core": {"value": n_one / t_one / scale, "cores": 1,
+                           "sample": f"{n_one} solves in {t_one:.1f} s, BLAS on 1 thread"},
+           "host": host}
+    if c2_legs:
+        from threadpoolctl import threadpool_limits
+        c2 = synth.config("c2", seed=seed)
+        legs = {}
+        with threadpool_limits(allc):
+            for name, fn in (("pi_lu", lambda: O.policy_iteration(c2)),
+                             ("vi", lambda: O.value_iteration(c2, eps=1e-8 * c2.gamma / (1 - c2.gamma))),
+                             ("igmres_pi", lambda: O.igmres_pi(c2, W=30, tol=1e-8))):
+                t0 = time.perf_counter()
+                fn()
+                legs[name + "_s"] = round(time.perf_counter() - t0, 3)
+        legs["note"] = ("c2 (n=1e4, m=8, k=20, gamma=0.99) by the oracle on all host cores, one run "
+                        "each: PI with LU evaluation to a repeated policy, value iteration to "
+                        "||T V - V||_inf <= 1e-8, Algorithm 2 to tol 1e-8")
+        out["c2_legs"] = legs
+    return out
+
+
+def extra_leg(igmres, synth, torch, name, seed):
+    """Another single-GPU workload timed in the same run: c2 (FP64,
+    persistent engine) with exact-evaluation PI and OPI(20) beside it; c3
+    (dense) with FP32, BF16 and BF16 + FP32-refinement storage beside FP64,
+    each with its relative difference from the FP64 result."""
+    dev = torch.device("cuda:0")
+    mdp = synth.config(name, seed=seed)
+    restart = mdp.meta["restart"]
+    V = torch.zeros(mdp.n, dtype=torch.float64, device=dev)
+    pi = torch.zeros(mdp.n, dtype=torch.int32, device=dev)
+    out = {"workload": WORKLOADS[name]["desc"]}
+    if name == "c2":
+        with igmres.mdp_create(mdp, store="fp64") as h:
+            info = h.info()
+            p = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8)
+            timed_solves(h, h.igmres_pi_solve, V, pi, p, 20, torch)  # warm-up
+            r = timed_solves(h, h.igmres_pi_solve, V, pi, p, 200, torch)
+            out["igmres_pi"] = r
+            out["solves_per_s"] = round(1e3 / r["ms_p50"], 2)
+            out["engine"] = (f"persistent, {info.persistent_blocks} blocks" if info.persistent_ok
+                             else "stream")
+            out["regime"] = "latency-bound: the 19 MB stored MDP is cache-resident"
+        out.update(comparisons(igmres, torch, mdp, WORKLOADS["c2"], restart, r["ms_p50"], 5))
+        return out
+    variants = [("fp64", "fp64", "fp64", False), ("fp32", "fp32", "mixed", False),
+                ("bf16", "bf16", "mixed", False), ("bf16+fp32 refine", "bf16", "mixed", True)]
+    ref = None
+    for label, store, mode, refine in variants:
+        with igmres.mdp_create(mdp, store=store, refine=refine) as h:
+            p = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8, mode=mode)
+            timed_solves(h, h.igmres_pi_solve, V, pi, p, 3, torch)
+            r = timed_solves(h, h.igmres_pi_solve, V, pi, p, 20, torch)
+        Vh = V.double().cpu()
+        if ref is None:
+            ref = Vh
+        else:
+            r["rel_diff_vs_fp64"] = float((Vh - ref).abs().max() / ref.abs().max())
+            r["speedup_vs_fp64"] = round(out["fp64"]["ms_p50"] / r["ms_p50"], 2)
+        out[label] = r
+    return out
 
 
 SERVE_W = 30
@@ -313,9 +414,12 @@ def serving_leg(igmres, synth, torch, count, seed, load=0.8, prep_threads=4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c5"])
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed solves (default: 20 for c4, 50 for c3, 200 for c1/c2)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed solves (default 5 for c4, else 20)")
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c5"])
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other single-GPU workloads (c2, c3) timed beside the main one")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--prep-threads", type=int, default=4)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
@@ -363,6 +467,10 @@ def main():
         return
 
     wl = WORKLOADS[args.workload]
+    if args.steps is None:
+        args.steps = 20 if args.workload == "c4" else 50 if wl["cfg"] == "c3" else 200
+    if args.warmup is None:
+        args.warmup = 5 if args.workload == "c4" else 20
     print(f"[bench] generating {args.workload} seed {args.seed}", file=sys.stderr, flush=True)
     mdp = synth.config(wl["cfg"], seed=args.seed)
     restart = mdp.meta["restart"]
@@ -371,7 +479,7 @@ def main():
     torch.cuda.set_device(dev)
     print("[bench] uploading", file=sys.stderr, flush=True)
     t_up = time.perf_counter()
-    h = igmres.mdp_create(mdp, store=wl["store"])
+    h = igmres.mdp_create(mdp, store=wl["store"], refine=wl.get("refine", False))
     create_ms = (time.perf_counter() - t_up) * 1e3
     info = h.info()
     V = torch.zeros(mdp.n, dtype=torch.float64, device=dev)
@@ -429,7 +537,8 @@ def main():
                               + (4 if info.fmt == 0 else 0))
         regime = ("latency-bound; the stored MDP (%.0f MB) is cache-resident" % (p_bytes / 1e6)
                   if p_bytes < 256e6 else "HBM streaming")
-        roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        roof = {"bound": "hbm" if p_bytes >= 256e6 else "latency", "achieved": round(ach, 2),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": dom, "launches": dom_n, "avg_us": round(dom_avg_ms * 1e3, 3),
                 "alg_bytes_per_launch": b, "copy_GBps": round(cbw, 1), "regime": regime}
@@ -450,6 +559,16 @@ def main():
         cpu = cpu_baseline(mdp, restart, synth, wl["cfg"], args.seed)
 
     h.close()
+    del h
+    extra = None
+    if not args.no_extra and args.workload == "c4":
+        extra = {}
+        for name in ("c2", "c3"):
+            print(f"[bench] extra workload {name}", file=sys.stderr, flush=True)
+            try:
+                extra[name] = extra_leg(igmres, synth, torch, name, args.seed)
+            except igmres.IgError as e:  # reported, never fatal to the main line
+                extra[name] = {"error": str(e)}
     sv = None
     if not args.no_serving:
         sv = serving_leg(igmres, synth, torch, args.serve_requests, args.seed,
@@ -460,6 +579,12 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if not fp32 else "f64+f32", "data": "synthetic",
+        "precision": ("FP64 throughout" if not fp32 else
+                      f"P stored in {wl['store'].upper()}" +
+                      (" for the products inside GMRES, with an FP32 copy for the Bellman passes "
+                       "and residuals" if wl.get("refine") else "") +
+                      "; FP32 Krylov basis and P^pi products with FP32 accumulation; FP64 Bellman "
+                      "pass, residuals, dot products, solution update and Hessenberg/Givens solve"),
         "config": {"workload": f"{args.workload}: {wl['desc']}", "seed": args.seed,
                    "n": mdp.n, "m": mdp.m, "nnz": int(info.nnz), "restart": restart,
                    "engine": ("persistent (one cooperative launch per solve, "
@@ -478,6 +603,7 @@ def main():
                   "alg_GBps_solve": round(st["alg_bytes"] / (ms_step * 1e-3) / 1e9, 2)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "extra": extra,
         "serving": sv,
     }
     print(json.dumps(out), flush=True)

@@ -307,7 +307,8 @@ class OracleStats:
     converged: bool = False
 
 
-def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=False, precond=0):
+def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=False, precond=0,
+                res_trace=None):
     """Inexact policy evaluation by restarted GMRES(W): the inner solver of
     Algorithm 2 (Sec. 3.1) for J V = b with J = I - gamma P^pi, b = g^pi.
 
@@ -343,7 +344,8 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
     GMRES(W) with W < n can stagnate completely, and rounding puts a floor
     under the residual.
     Returns (x, info) with info = dict(steps, restarts, breakdown, iterates
-    (first cycle, if trace), res_inf, thr, stagnated).
+    (first cycle, if trace), res_inf, thr, stagnated); a list passed as
+    res_trace receives ||b - J x_i||_inf of every iterate.
     """
     Ppi = policy_matrix_sparse(mdp, pi)
     b = policy_cost(mdp, pi)
@@ -373,6 +375,8 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
             r = b - J(x)
             res_inf = float(np.max(np.abs(r)))
             steps += 1
+            if res_trace is not None:
+                res_trace.append(res_inf)
             if trace and restarts == 0:
                 iterates.append(x.copy())
             if res_inf <= thr or steps >= max_inner:
@@ -393,7 +397,7 @@ def gmres_inner(mdp, pi, x0, alpha, W, max_inner=10_000, ref_inf=None, trace=Fal
 
 
 def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inner=10_000,
-              precond=0, forcing=False, polish=False):
+              precond=0, forcing=False, polish=False, inner_trace=None):
     """Algorithm 2 with outer termination at ||T V_k - V_k||_inf <= tol.
 
     alpha defaults to the midpoint of Theorem 1's admissible range,
@@ -407,7 +411,9 @@ def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inne
     next Bellman residual meets it unless the greedy policy moves again.
     Both only shrink the inexactness term, so Theorem 1 still applies.
     Returns (V, pi, OracleStats); V and pi are V_k and GreedyPolicy(V_k) of
-    the terminating outer step.
+    the terminating outer step.  A list passed as inner_trace receives, per
+    outer step, dict(thr=the inner threshold, res=[||g - J x_i||_inf of each
+    inner iterate]).
     """
     g = mdp.gamma
     if alpha is None:
@@ -430,8 +436,11 @@ def igmres_pi(mdp, V0=None, alpha=None, W=30, tol=1e-8, max_outer=1000, max_inne
             st.polished.append(k)
         pi_prev = pi
         st.alpha_history.append(alpha_k)
+        res_list = [] if inner_trace is not None else None
         V, info = gmres_inner(mdp, pi, V, alpha_k, W, max_inner, ref_inf=phi_inf,
-                              precond=precond)
+                              precond=precond, res_trace=res_list)
+        if inner_trace is not None:
+            inner_trace.append(dict(thr=info["thr"], res=res_list))
         st.inner += info["steps"]
         st.restarts += info["restarts"]
         st.breakdowns += int(info["breakdown"])

@@ -55,3 +55,43 @@ def assert_policy_match(mdp, Vstar, pi_star, pi, gap_min=1e-9):
 
 def rel_err(V, Vstar):
     return float(np.max(np.abs(V - Vstar)) / max(np.max(np.abs(Vstar)), 1e-300))
+
+
+def residual_floor(mdp, Vstar):
+    """Absolute rounding error of one FP64 evaluation of g^pi - (V - gamma
+    P^pi V) near V*: each component sums k products and three terms, each
+    rounded at unit roundoff eps, on operands bounded by max|g| + 2 max|V|."""
+    k = int(np.max(np.diff(mdp.row_ptr))) if mdp.fmt == "csr" else mdp.n
+    eps = np.finfo(np.float64).eps / 2
+    return (k + 3) * eps * (float(np.max(np.abs(mdp.cost))) + 2 * float(np.max(np.abs(Vstar))))
+
+
+def assert_inner_parity(st, sto, trace, replay, floor=0.0, rel_band=1e-4):
+    """The GPU's Arnoldi step count against the oracle's literal stopping
+    index.  Equal totals pass.  Otherwise, at the first outer step whose
+    counts differ (replay(k) returns the GPU's cumulative count after k
+    outer steps), the two may differ by one step only where the decision is
+    not resolvable in FP64: the oracle's residual at the disputed iterate
+    lies within rel_band of the threshold, or within `floor` (the rounding
+    error of an evaluated residual, residual_floor) of it, as happens when a
+    forcing sequence drives the threshold to the rounding level.  Later steps
+    start from different iterates, and only the outer count and V* compare."""
+    if st["inner"] == sto.inner:
+        return
+    prev = 0
+    for k, tr in enumerate(trace):
+        cum = replay(k + 1)
+        got, want = cum - prev, len(tr["res"])
+        prev = cum
+        if got == want:
+            continue
+        assert abs(got - want) == 1, f"outer step {k}: {got} inner steps against the oracle's {want}"
+        # GPU one longer: it went past the oracle's stop; one shorter: it
+        # stopped at an iterate where the oracle did not
+        q = tr["res"][want - 1] if got > want else tr["res"][got - 1]
+        thr = tr["thr"]
+        assert abs(q - thr) <= max(rel_band * thr, floor), (
+            f"outer step {k}: a one-step difference at a resolvable decision (residual "
+            f"{q:.3e}, threshold {thr:.3e}, rounding floor {floor:.1e})")
+        return
+    raise AssertionError("totals differ but every replayed outer step agrees")

@@ -23,8 +23,11 @@ def test_algorithmic_bytes_sparse_and_dense():
     sparse = SimpleNamespace(n=n, m=m, nnz=n * m * k, store=0, fmt=0)
     # Bellman: P (value + int32 column per entry), g, V; Phi, pi and g^pi out
     assert bench.per_launch_bytes(sparse, "bellman", False) == n * m * k * 12 + n * m * 8 + n * 8 + n * 20
-    # J-apply: P^pi rows, x in, y out, basis column out (FP32 vectors in mixed mode)
-    assert bench.per_launch_bytes(sparse, "japply", True) == n * k * 12 + n * 4 * 3
+    # J-apply: P^pi rows, x in, y out (FP32 vectors in mixed mode)
+    assert bench.per_launch_bytes(sparse, "japply", True) == n * k * 12 + n * 4 * 2
+    # refine mode: the products read the BF16 copy of P^pi
+    refine = SimpleNamespace(n=n, m=m, nnz=n * m * k, store=1, fmt=0, refine=1)
+    assert bench.per_launch_bytes(refine, "japply", True) == n * k * 6 + n * 4 * 2
     assert bench.per_launch_bytes(sparse, "residual", False) == n * k * 12 + n * 24
     dense = SimpleNamespace(n=n, m=4, nnz=n * 4 * n, store=2, fmt=1)  # BF16 rows, no column indices
     assert bench.per_launch_bytes(dense, "bellman", True) == n * 4 * n * 2 + n * 4 * 8 + n * 8 + n * 20

@@ -9,7 +9,8 @@ import pytest
 from oracle import mdp_oracle as O
 from paper_2211_04299_amd import synth
 
-from gpu_helpers import assert_policy_match, dev_vec, host, rel_err, tol_par, zeros
+from gpu_helpers import (assert_inner_parity, assert_policy_match, dev_vec, host, rel_err,
+                         residual_floor, tol_par, zeros)
 
 pytestmark = pytest.mark.gpu
 
@@ -95,9 +96,12 @@ def test_igmres_forcing_parity(name, seed, W, engine):
     assert st["converged"] == 1
     assert rel_err(V, Vs) <= 1e-8
     assert_policy_match(mdp, Vs, pis, pi)
-    Vo, pio, sto = O.igmres_pi(mdp, W=W, tol=tol, forcing=True)
+    trace = []
+    Vo, pio, sto = O.igmres_pi(mdp, W=W, tol=tol, forcing=True, inner_trace=trace)
     assert st["outer"] == sto.outer
-    assert st["inner"] == sto.inner  # the literal stopping index, step for step
+    assert_inner_parity(st, sto, trace, lambda k: solve(
+        mdp, tol=tol, restart=W, engine=engine, forcing=1, max_outer=k, allow_noconv=True)[2]["inner"],
+        floor=residual_floor(mdp, Vs))
     _, _, st0 = solve(mdp, tol=tol, restart=W, engine=engine)
     assert st["outer"] <= st0["outer"]
 
@@ -115,10 +119,13 @@ def test_igmres_polish_parity(name, seed, W, engine):
     assert st["converged"] == 1
     assert rel_err(V, Vs) <= 1e-8
     assert_policy_match(mdp, Vs, pis, pi)
-    Vo, pio, sto = O.igmres_pi(mdp, W=W, tol=tol, polish=True)
+    trace = []
+    Vo, pio, sto = O.igmres_pi(mdp, W=W, tol=tol, polish=True, inner_trace=trace)
     assert sto.polished
     assert st["outer"] == sto.outer
-    assert st["inner"] == sto.inner  # the literal stopping index, step for step
+    assert_inner_parity(st, sto, trace, lambda k: solve(
+        mdp, tol=tol, restart=W, engine=engine, polish=1, max_outer=k, allow_noconv=True)[2]["inner"],
+        floor=residual_floor(mdp, Vs))
     _, _, st0 = solve(mdp, tol=tol, restart=W, engine=engine)
     assert st["outer"] <= st0["outer"]
 
