@@ -257,6 +257,30 @@ ig_status policy_eval_gmres(ig_mdp_t mdp, const int32_t* pi, double* V, const ig
 ig_status igmres_pi_solve(ig_mdp_t mdp, double* V, int32_t* pi, const ig_params* params,
                           ig_stats* stats, void* stream);
 
+/* Allocation-free Algorithm 2, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc).  The same
+ * solve as igmres_pi_solve on the persistent engine (same kernel, same
+ * workgroup count, bitwise the same V, pi and counts), except that its
+ * device workspace -- Krylov basis, Arnoldi vector, cycle base, residual,
+ * reduction partials, barrier arrival words and control block -- lives in a
+ * static device array of IG_NOALLOC_SCRATCH_BYTES that every GPU holds from
+ * the library's load until the process ends; the call allocates nothing.
+ * Every call on one GPU shares that array: calls that overlap on a GPU (any
+ * handle, any stream) race and must be serialised by the caller.  What must
+ * start at zero (arrival words, control block) is cleared by each call.
+ * The handle comes from mdp_create (which allocates); V (n doubles) and pi
+ * (n int32) are device pointers, both required.  The call is host-synchronous
+ * (not capturable into a HIP graph).
+ * Errors: IG_E_TOO_LARGE when the workspace, about (restart+3) * n * 8 bytes
+ * (FP64) or (restart+2) * n * 4 + 16 * n bytes (MIXED), exceeds the array, or
+ * the shape does not fit the persistent engine (sparse, restart <= 64, no
+ * refine); IG_E_INVALID for engine 1, a preconditioner, per-class timing
+ * enabled on the handle (its events are created on demand), or a handle whose
+ * device is not current; otherwise as igmres_pi_solve. */
+#define IG_NOALLOC_SCRATCH_BYTES (32u << 20)
+ig_status igmres_pi_solve_noalloc(ig_mdp_t mdp, double* V, int32_t* pi, const ig_params* params,
+                                  ig_stats* stats, void* stream);
+
 /* Policy iteration (Section 2.1): pi_0 = GreedyPolicy(V0); evaluation by
  * GMRES driven to ||residual||_inf <= eval_rtol * ||g^pi||_inf (or
  * stagnation); improvement keeps the incumbent action unless another is

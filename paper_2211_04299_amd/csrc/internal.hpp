@@ -159,6 +159,9 @@ void launch_round_bf16(const float* src, void* dst, int64_t count, hipStream_t s
 
 ig_status ensure_workspace(Mdp& d, int W, bool fp32);
 ig_status sync_status(Mdp& d, hipStream_t s);
+Mdp* handle_of(ig_mdp_t h);
+// solver parameters against the handle (IG_E_INVALID / IG_E_TOO_LARGE)
+ig_status check_params(const Mdp& d, const ig_params* p, bool need_alpha);
 
 // ---- sparse (sliced ELL) launchers --------------------------------------
 // Bellman pass: TV (nullable), Phi = TV - V, pi, g^pi, compact P^pi and the

@@ -28,6 +28,8 @@
 // evaluated (two more barriers).
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -843,8 +845,21 @@ int persistent_blocks(const Mdp& d, int* spb_out, int requested = 0) {
   return nb;
 }
 
+// Device buffers of one persistent solve: the handle's workspace, or the
+// carve-up of the allocation-free entry point's static scratch.
+struct PWork {
+  void* Q;          // (W+1) x n basis
+  void* w1;         // n: once-orthogonalised Arnoldi vector
+  double* Vb;       // n: iterate at the start of the restart cycle
+  double* r;        // n: Phi_k / explicit residual
+  double* part;     // [2][blocks][kPStride] reduction partials
+  unsigned* flags;  // [blocks] arrival words (zeroed before the launch)
+  PCtl* ctl;        // control block (zeroed before the launch)
+};
+
 template <typename VT, typename XT>
-ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coop, hipStream_t s) {
+ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coop,
+                    const PWork& w, hipStream_t s) {
   int spb = 0;
   const int nb = persistent_blocks(d, &spb, p.blocks);
   PArgs<VT, XT> a;
@@ -859,13 +874,13 @@ ig_status run_typed(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coo
   a.V = V;
   a.pi = pi;
   a.cpi = d.cpi;
-  a.Q = (XT*)d.ws.Q;
-  a.w1 = (XT*)d.ws.wA;
-  a.Vb = d.ws.Vb;
-  a.r = d.ws.r;
-  a.part = d.part;
-  a.flags = (unsigned int*)d.ws.wB;  // arrival words, zeroed below
-  a.ctl = d.pctl;
+  a.Q = (XT*)w.Q;
+  a.w1 = (XT*)w.w1;
+  a.Vb = w.Vb;
+  a.r = w.r;
+  a.part = w.part;
+  a.flags = w.flags;  // arrival words, zeroed below
+  a.ctl = w.ctl;
   a.alpha = p.alpha;
   a.tol = p.tol;
   a.sqrt_n = std::sqrt((double)d.n);
@@ -911,23 +926,31 @@ bool persistent_fits(const Mdp& d) {
 
 namespace {
 
-ig_status launch_impl(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coop, hipStream_t s) {
+// work == nullptr: the handle's workspace (allocated or grown here)
+ig_status launch_impl(Mdp& d, double* V, int32_t* pi, const ig_params& p, bool coop, hipStream_t s,
+                      const PWork* work = nullptr) {
   if (!persistent_fits(d)) return fail(IG_E_TOO_LARGE, "shape does not fit the persistent engine");
   if (p.restart > kPMaxW) return fail(IG_E_TOO_LARGE, "the persistent engine takes restart <= 64");
   if (coop && !d.coop) return fail(IG_E_DEVICE, "device does not support cooperative launches");
   const bool fp32 = p.mode == IG_MODE_MIXED;
-  if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
-  IG_HIP(hipMemsetAsync(d.pctl, 0, sizeof(PCtl), s));
+  PWork w{};
+  if (work) {
+    w = *work;
+  } else {
+    if (ig_status e = ensure_workspace(d, p.restart, fp32)) return e;
+    w = PWork{d.ws.Q, d.ws.wA, d.ws.Vb, d.ws.r, d.part, (unsigned*)d.ws.wB, d.pctl};
+  }
+  IG_HIP(hipMemsetAsync(w.ctl, 0, sizeof(PCtl), s));
   switch (d.store) {
     case IG_FP64:
-      return fp32 ? run_typed<double, float>(d, V, pi, p, coop, s)
-                  : run_typed<double, double>(d, V, pi, p, coop, s);
+      return fp32 ? run_typed<double, float>(d, V, pi, p, coop, w, s)
+                  : run_typed<double, double>(d, V, pi, p, coop, w, s);
     case IG_FP32:
-      return fp32 ? run_typed<float, float>(d, V, pi, p, coop, s)
-                  : run_typed<float, double>(d, V, pi, p, coop, s);
+      return fp32 ? run_typed<float, float>(d, V, pi, p, coop, w, s)
+                  : run_typed<float, double>(d, V, pi, p, coop, w, s);
     default:
-      return fp32 ? run_typed<bf16, float>(d, V, pi, p, coop, s)
-                  : run_typed<bf16, double>(d, V, pi, p, coop, s);
+      return fp32 ? run_typed<bf16, float>(d, V, pi, p, coop, w, s)
+                  : run_typed<bf16, double>(d, V, pi, p, coop, w, s);
   }
 }
 
@@ -966,3 +989,104 @@ ig_status persistent_igmres(Mdp& d, double* V, int32_t* pi, const ig_params& p, 
 }
 
 }  // namespace ig
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry point (igmres_pi_solve_noalloc): the whole device
+// workspace of one persistent solve comes from a static device array.
+// ---------------------------------------------------------------------------
+namespace ig {
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)32 << 20;  // IG_NOALLOC_SCRATCH_BYTES
+static_assert(kScratchBytes == (size_t)IG_NOALLOC_SCRATCH_BYTES, "header and library disagree");
+
+// One copy per GPU, held until the process ends.  Host code never uses this
+// name as an address: the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// Device address of `scratch` on device `dev` (which must be current); looked
+// up on the first call per device.
+ig_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(IG_E_INVALID, "device ordinal out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(IG_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return IG_OK;
+}
+
+// Carve the persistent solve's buffers out of [base, base + kScratchBytes);
+// IG_E_TOO_LARGE when they do not fit.
+ig_status carve(const Mdp& d, const ig_params& p, char* base, PWork* w, size_t* used) {
+  int spb = 0;
+  const int nb = persistent_blocks(d, &spb, p.blocks);
+  const size_t n = (size_t)d.n, xb = p.mode == IG_MODE_MIXED ? 4 : 8;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base + off;
+    off += round_alloc(bytes);
+    return (void*)q;
+  };
+  w->Q = take((size_t)(p.restart + 1) * n * xb);
+  w->w1 = take(n * xb);
+  w->Vb = (double*)take(n * 8);
+  w->r = (double*)take(n * 8);
+  w->part = (double*)take((size_t)2 * nb * kPStride * 8);
+  w->flags = (unsigned*)take((size_t)nb * sizeof(unsigned));
+  w->ctl = (PCtl*)take(sizeof(PCtl));
+  *used = off;
+  if (off > kScratchBytes)
+    return fail(IG_E_TOO_LARGE, "the solve's workspace exceeds IG_NOALLOC_SCRATCH_BYTES");
+  return IG_OK;
+}
+
+}  // namespace
+}  // namespace ig
+
+extern "C" ig_status igmres_pi_solve_noalloc(ig_mdp_t h, double* V, int32_t* pi,
+                                             const ig_params* params, ig_stats* stats,
+                                             void* stream) {
+  using namespace ig;
+  Mdp* d = handle_of(h);
+  if (!d) return fail(IG_E_INVALID, "NULL handle");
+  if (!V || !pi) return fail(IG_E_INVALID, "V and pi are required");
+  if (ig_status e = check_params(*d, params, true)) return e;
+  const ig_params& p = *params;
+  if (p.engine == 1) return fail(IG_E_INVALID, "the allocation-free solve runs the persistent engine");
+  if (p.precond != 0) return fail(IG_E_INVALID, "the allocation-free solve has no preconditioner");
+  if (d->prof_mask) return fail(IG_E_INVALID, "per-class timing creates events: disable it first");
+  int cur = -1;
+  IG_HIP(hipGetDevice(&cur));
+  if (cur != d->device) return fail(IG_E_INVALID, "the handle's device must be current");
+  void* base = nullptr;
+  if (ig_status e = scratch_address(cur, &base)) return e;
+  PWork w{};
+  size_t used = 0;
+  if (ig_status e = carve(*d, p, (char*)base, &w, &used)) return e;
+  hipStream_t s = (hipStream_t)stream;
+  ig_stats st;
+  std::memset(&st, 0, sizeof st);
+  IG_HIP(hipEventRecord(d->ev0, s));
+  ig_status e = launch_impl(*d, V, pi, p, true, s, &w);
+  if (e == IG_OK) {
+    IG_HIP(hipMemcpyAsync(d->hpctl, w.ctl, sizeof(PCtl), hipMemcpyDeviceToHost, s));
+    IG_HIP(hipEventRecord(d->ev1, s));
+    IG_HIP(hipEventSynchronize(d->ev1));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, d->ev0, d->ev1);
+    e = persistent_collect(*d, st);
+    st.time_ms = ms;
+    st.cert_bound = st.res_inf / (1.0 - d->gamma);
+  }
+  if (stats) *stats = st;
+  return e;
+}

@@ -237,6 +237,8 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
   }
 }
 
+}  // namespace
+
 ig_status check_params(const Mdp& d, const ig_params* p, bool need_alpha) {
   if (!p) return fail(IG_E_INVALID, "params is NULL");
   if (need_alpha && !(p->alpha > 0.0 && p->alpha < 1.0)) return fail(IG_E_INVALID, "alpha must be in (0,1)");
@@ -253,6 +255,8 @@ ig_status check_params(const Mdp& d, const ig_params* p, bool need_alpha) {
     return fail(IG_E_INVALID, "the persistent engine does not take refine-mode handles (use engine 0 or 1)");
   return IG_OK;
 }
+
+namespace {
 
 struct Timer {
   Mdp& d;

@@ -29,6 +29,7 @@ IG_FP64, IG_FP32, IG_BF16 = 0, 1, 2
 DTYPES = {"fp64": IG_FP64, "fp32": IG_FP32, "bf16": IG_BF16}
 IG_MODE_FP64, IG_MODE_MIXED = 0, 1
 IG_MAX_RESTART = 128
+IG_NOALLOC_SCRATCH_BYTES = 32 << 20
 ENGINE_AUTO, ENGINE_STREAM, ENGINE_PERSISTENT = 0, 1, 2
 IG_PROFILE_CLASSES = 8
 PROFILE_CLASS_NAMES = ["bellman", "japply", "gram_schmidt", "update", "residual", "vi_sweep", "other",
@@ -36,7 +37,8 @@ PROFILE_CLASS_NAMES = ["bellman", "japply", "gram_schmidt", "update", "residual"
 
 EXPORTS = ["ig_params_default", "mdp_create", "mdp_destroy", "mdp_get_info", "bellman_apply",
            "policy_eval_gmres", "igmres_pi_solve", "pi_solve", "opi_solve", "ipi_vi_solve",
-           "ig_profile_enable", "ig_profile_read", "ig_last_error", "ig_server_config_default",
+           "igmres_pi_solve_noalloc", "ig_profile_enable", "ig_profile_read", "ig_last_error",
+           "ig_server_config_default",
            "srv_create", "srv_submit", "srv_poll", "srv_result", "srv_get_info", "srv_destroy"]
 
 
@@ -99,6 +101,7 @@ _sig = {
     "bellman_apply": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "policy_eval_gmres": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
     "igmres_pi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
+    "igmres_pi_solve_noalloc": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
     "pi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
     "opi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
     "ipi_vi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
@@ -214,6 +217,10 @@ class Mdp:
 
     def igmres_pi_solve(self, V, pi, params, stream=None, allow_noconv=False):
         return self._solve(_lib.igmres_pi_solve, "igmres_pi_solve", V, pi, params, stream, allow_noconv)
+
+    def igmres_pi_solve_noalloc(self, V, pi, params, stream=None, allow_noconv=False):
+        return self._solve(_lib.igmres_pi_solve_noalloc, "igmres_pi_solve_noalloc", V, pi, params,
+                           stream, allow_noconv)
 
     def pi_solve(self, V, pi, params, stream=None, allow_noconv=False):
         return self._solve(_lib.pi_solve, "pi_solve", V, pi, params, stream, allow_noconv)
