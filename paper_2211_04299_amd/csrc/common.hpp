@@ -58,7 +58,10 @@ constexpr int kMaxW = IG_MAX_RESTART;
 // sliced ELL views.  Slice b (states 64b .. 64b+63) has width K_b.
 //   full P:     entry (a, j, l) at off[b] + ((a*K_b + j) << 6) + l
 //   compact P^pi entry (j, l) at offp[b] + (j << 6) + l
-// Padding entries have column 0 and value 0.
+// Padding entries have column 0 and value 0.  The full P arrays carry
+// kRowPad zero entries after the last slice, so a wavefront may read 16 whole
+// slots of any row (see k_bellman).
+constexpr int64_t kRowPad = 16 * 64;
 // ---------------------------------------------------------------------------
 template <typename VT>
 struct SellP {
@@ -228,6 +231,36 @@ __device__ __forceinline__ void ell_stream(const int32_t* __restrict__ col,
     use(f0 + kU, cn, vn);
   }
   use(f0, c, v);
+}
+
+// Copy the K entries j = g, g+G, ... of one sliced-ELL row (entry j at
+// src + (j << 6)) to a row of another sliced-ELL array (at dst + (j << 6)).
+// kU loads of each array are issued before their kU stores (for the
+// compiler a store may alias a later load, so it keeps them in program
+// order otherwise).
+template <typename VT, int G>
+__device__ __forceinline__ void ell_copy_row(const int32_t* __restrict__ scol,
+                                             const VT* __restrict__ sval, int64_t src,
+                                             int32_t* __restrict__ dcol, VT* __restrict__ dval,
+                                             int64_t dst, int K, int g) {
+  for (int j0 = g; j0 < K; j0 += kU * G) {
+    int32_t c[kU];
+    VT v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t e = src + ((int64_t)min(j0 + u * G, K - 1) << 6);  // clamped: in range
+      c[u] = scol[e];
+      v[u] = sval[e];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int j = j0 + u * G;
+      if (j < K) {
+        dcol[dst + ((int64_t)j << 6)] = c[u];
+        dval[dst + ((int64_t)j << 6)] = v[u];
+      }
+    }
+  }
 }
 
 // row stride of the Gram-Schmidt partials (doubles per block)

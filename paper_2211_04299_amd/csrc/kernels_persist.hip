@@ -526,12 +526,8 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
             pmax = fmax(pmax, fabs(phi));
             psum = fma(phi, phi, psum);
           }
-          const int64_t src = ob + (((int64_t)besta * Kb) << 6) + l;
-          const int64_t dst = A.Pp.off[b] + l;
-          for (int j = g; j < Kb; j += G) {
-            A.Pp.col[dst + ((int64_t)j << 6)] = A.P.col[src + ((int64_t)j << 6)];
-            A.Pp.val[dst + ((int64_t)j << 6)] = A.P.val[src + ((int64_t)j << 6)];
-          }
+          ell_copy_row<VT, G>(A.P.col, A.P.val, ob + (((int64_t)besta * Kb) << 6) + l, A.Pp.col,
+                              A.Pp.val, A.Pp.off[b] + l, Kb, g);
         }
       };
       if (A.vlds) {

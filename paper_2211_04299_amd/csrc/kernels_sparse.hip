@@ -12,6 +12,10 @@
 // wavefronts is capped by the hardware, so only this raises the bytes in
 // flight).  Reductions end with per-block partials; a one-block finishing
 // kernel (launch_finalize) combines them in a fixed order.
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace ig {
@@ -44,7 +48,13 @@ __device__ __forceinline__ AT group_sum(AT acc) {
   return acc;
 }
 
-template <typename VT, int G>
+// KR > 0 (one lane per state, rows of at most KR entries): each action's row
+// is loaded whole, one row ahead of the one being summed, and the entries of
+// the best row so far stay in registers, so the compact P^pi row is written
+// from them.  Otherwise it is re-read at the end, and since the 64 lanes of a
+// wavefront choose among m blocks of a slot, that re-read fetches whole
+// sectors for a few useful bytes each.
+template <typename VT, int G, int KR>
 __global__ __launch_bounds__(kBlock) void k_bellman(
     SellP<VT> P, const double* __restrict__ cost, int m, int64_t n, double gamma,
     const double* __restrict__ V, double* __restrict__ TV, double* __restrict__ Phi,
@@ -79,7 +89,57 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
       }
       if (a == inc) qinc = q;
     };
-    if constexpr (G == 1) {
+    int rowa = -1;  // KR > 0: the action whose row is held in (bc, bv)
+    int32_t bc[KR > 0 ? KR : 1];
+    VT bv[KR > 0 ? KR : 1];
+    if constexpr (G == 1 && KR > 0) {
+      int32_t rc[KR], nc[KR];
+      VT rv[KR], nv[KR];
+      // all KR slots from one base address (immediate offsets); slots past
+      // Kb read the next row's entries or the zero tail of kRowPad entries
+      // after the last slice, and are not used
+      auto load_row = [&](int a, int32_t(&cc)[KR], VT(&vv)[KR]) {
+        const int32_t* cb = P.col + ob + (((int64_t)a * Kb) << 6);
+        const VT* vb = P.val + ob + (((int64_t)a * Kb) << 6);
+#pragma unroll
+        for (int j = 0; j < KR; ++j) {
+          cc[j] = ld_stream(cb + (j << 6));
+          vv[j] = ld_stream(vb + (j << 6));
+        }
+      };
+      load_row(0, rc, rv);
+      double cst = cost[sc];
+      for (int a = 0; a < Mb; ++a) {
+        if (a + 1 < Mb) load_row(a + 1, nc, nv);
+        const double cst_next = a + 1 < Mb ? cost[(int64_t)(a + 1) * n + sc] : 0.0;
+        double acc = 0.0;
+        // gathers in halves of KR/2 (fewer registers), summed in slot order
+#pragma unroll
+        for (int h = 0; h < KR; h += KR / 2) {
+          double xv[KR / 2];
+#pragma unroll
+          for (int j = 0; j < KR / 2; ++j) xv[j] = h + j < Kb ? V[rc[h + j]] : 0.0;
+#pragma unroll
+          for (int j = 0; j < KR / 2; ++j)
+            if (h + j < Kb) acc = fma(to_d(rv[h + j]), xv[j], acc);
+        }
+        candidate(a, cst + gamma * acc);
+        if (besta == a) {
+          rowa = a;
+#pragma unroll
+          for (int j = 0; j < KR; ++j) {
+            bc[j] = rc[j];
+            bv[j] = rv[j];
+          }
+        }
+        cst = cst_next;
+#pragma unroll
+        for (int j = 0; j < KR; ++j) {
+          rc[j] = nc[j];
+          rv[j] = nv[j];
+        }
+      }
+    } else if constexpr (G == 1) {
       // one lane per state: rows a = 0..m-1 of the slice are consecutive, so
       // the m*Kb entries form one pipelined stream; the cost of row a is
       // loaded when the row starts and used when it ends
@@ -133,12 +193,18 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
       psum = fma(phi, phi, psum);
       if (pi_old && astar != inc) chg += 1.0;
     }
-    if (Pp.col) {  // copy the chosen row into the compact P^pi (groups split j)
-      const int64_t src = ob + (((int64_t)astar * Kb) << 6);
-      const int64_t dst = Pp.off[b] + l;
-      for (int j = g; j < Kb; j += G) {
-        Pp.col[dst + ((int64_t)j << 6)] = P.col[src + ((int64_t)j << 6)];
-        Pp.val[dst + ((int64_t)j << 6)] = P.val[src + ((int64_t)j << 6)];
+    if (Pp.col) {  // the chosen row into the compact P^pi (groups split j)
+      if (KR > 0 && astar == rowa) {
+        const int64_t dst = Pp.off[b] + l;
+#pragma unroll
+        for (int j = 0; j < (KR > 0 ? KR : 1); ++j)
+          if (j < Kb) {
+            Pp.col[dst + ((int64_t)j << 6)] = bc[j];
+            Pp.val[dst + ((int64_t)j << 6)] = bv[j];
+          }
+      } else {
+        ell_copy_row<VT, G>(P.col, P.val, ob + (((int64_t)astar * Kb) << 6), Pp.col, Pp.val,
+                            Pp.off[b] + l, Kb, g);
       }
     }
   }
@@ -264,12 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_policy(SellP<VT> P, SellPi<VT
       if (g == 0 && valid) bad += 1.0;
       a = 0;  // a stored block (zero padding when excluded): stays in bounds
     }
-    const int64_t src = P.off[b] + (((int64_t)a * Kb) << 6) + l;
-    const int64_t dst = Pp.off[b] + l;
-    for (int j = g; j < Kb; j += G) {
-      Pp.col[dst + ((int64_t)j << 6)] = P.col[src + ((int64_t)j << 6)];
-      Pp.val[dst + ((int64_t)j << 6)] = P.val[src + ((int64_t)j << 6)];
-    }
+    ell_copy_row<VT, G>(P.col, P.val, P.off[b] + (((int64_t)a * Kb) << 6) + l, Pp.col, Pp.val,
+                        Pp.off[b] + l, Kb, g);
     if (valid && g == 0) cpi[s] = cost[(int64_t)a * n + s];
   }
   double v[1] = {bad};
@@ -319,9 +381,19 @@ struct RunBellman {
                   const int32_t* pi_old, double tie_abs, bool compact, hipStream_t s) {
     SellPi<VT> pp = viewPi<VT>(d);
     if (!compact) pp.col = nullptr;
-    hipLaunchKernelGGL((k_bellman<VT, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
-                       viewP<VT>(d), (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi,
-                       pi_old, tie_abs, d.cpi, pp, d.part);
+    // rows of at most 16 entries, narrow values: the register-held rows
+    // (IG_BELLMAN_ROWS=off selects the re-read, for comparisons)
+    const char* ev = std::getenv("IG_BELLMAN_ROWS");
+    const bool rows = G == 1 && !std::is_same<VT, double>::value && d.maxK <= 16 &&
+                      !(ev && !std::strcmp(ev, "off"));
+    if (rows)
+      hipLaunchKernelGGL((k_bellman<VT, 1, 16>), dim3(grid_for(d, 1)), dim3(kBlock), 0, s,
+                         viewP<VT>(d), (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi,
+                         pi_old, tie_abs, d.cpi, pp, d.part);
+    else
+      hipLaunchKernelGGL((k_bellman<VT, G, 0>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
+                         viewP<VT>(d), (const double*)d.cost, d.m, d.n, d.gamma, V, TV, Phi, pi,
+                         pi_old, tie_abs, d.cpi, pp, d.part);
   }
 };
 

@@ -612,7 +612,8 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
     d->stored = tot;
     d->stored_pi = totp;
     d->h_width = width;
-    if (dmalloc(&d->col, (size_t)tot * 4) || dmalloc(&d->val, (size_t)tot * d->vb) ||
+    if (dmalloc(&d->col, (size_t)(tot + kRowPad) * 4) ||
+        dmalloc(&d->val, (size_t)(tot + kRowPad) * d->vb) ||
         dmalloc(&d->off, (size_t)ns * 8) || dmalloc(&d->offp, (size_t)ns * 8) ||
         dmalloc(&d->width, (size_t)ns * 4) || dmalloc(&d->mcnt, (size_t)ns * 4) ||
         dmalloc(&d->pcol, (size_t)totp * 4) || dmalloc(&d->pval, (size_t)totp * d->vb))
@@ -622,6 +623,8 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       if (ig_status e = upload(d, d->val, sval, (size_t)tot * d->vb)) return e;
     }
     if (ig_status e = upload(d, d->off, off, (size_t)ns * 8)) return e;
+    if (ig_status e = dzero(d, d->col + tot, (size_t)kRowPad * 4)) return e;
+    if (ig_status e = dzero(d, (char*)d->val + (size_t)tot * d->vb, (size_t)kRowPad * d->vb)) return e;
     if (ig_status e = upload(d, d->offp, offp, (size_t)ns * 8)) return e;
     if (ig_status e = upload(d, d->width, wid, (size_t)ns * 4)) return e;
     if (ig_status e = upload(d, d->mcnt, mc, (size_t)ns * 4)) return e;
@@ -901,7 +904,8 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
       tot += (int64_t)mb * w * kSlice;
       totp += w * kSlice;
     }
-    b += round256(tot * 4) + round256(tot * vb) + 2 * round256(ns * 8) + 2 * round256(ns * 4) +
+    b += round256((tot + kRowPad) * 4) + round256((tot + kRowPad) * vb) + 2 * round256(ns * 8) +
+         2 * round256(ns * 4) +
          round256(totp * 4) + round256(totp * vb);
     if (desc->refine) b += round256(totp * 2);
     // raw CSR staging of the device conversion: taken from the top of a
