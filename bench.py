@@ -364,29 +364,67 @@ def sequential_fp64(igmres, torch, mdps, budget_s=15.0):
     return done, el
 
 
-def serving_leg(igmres, synth, torch, count, seed, load=0.8, prep_threads=4):
+def h2d_bandwidth(torch, mib=512, reps=5):
+    """Host-to-device rate of one pinned 512 MiB copy (GB/s): the link every
+    served request's transition data has to cross."""
+    a = torch.empty(mib << 18, dtype=torch.float32, pin_memory=True)
+    a.fill_(1.0)
+    b = torch.empty(a.numel(), dtype=torch.float32, device="cuda")
+    b.copy_(a, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a, non_blocking=True)
+    torch.cuda.synchronize()
+    gbps = a.numel() * 4 * reps / (time.perf_counter() - t0) / 1e9
+    del a, b
+    return gbps
+
+
+def request_upload_bytes(m):
+    """Bytes of one served request that cross the host-device link: its raw
+    CSR (int64 row pointers, int32 columns, FP32 values) and FP64 costs."""
+    R = m.n * m.m
+    return 8 * (R + 1) + m.nnz * (4 + 4) + 8 * R
+
+
+def serving_leg(igmres, synth, torch, count, seed, loads=(0.5, 0.8, 1.0), prep_threads=4):
     print(f"[bench] serving: generating {count} requests", file=sys.stderr, flush=True)
     specs, mdps = serving_requests(synth, count, seed)
     nnz = np.array([m.nnz for m in mdps], dtype=np.float64)
+    up = np.array([request_upload_bytes(m) for m in mdps], dtype=np.float64)
     # saturated: every request queued at t = 0
     print("[bench] serving: saturation run", file=sys.stderr, flush=True)
     sat, info_sat = serve_once(igmres, mdps, np.zeros(count), prep_threads)
     makespan = max(c for _, c, _ in sat)
     lam_sat = count / makespan
-    # Poisson arrivals at `load` x the saturated throughput (same shapes)
-    rate = load * lam_sat
-    arr = np.array([r.arrival for r in synth.serving_stream(count, rate, seed)])
-    print(f"[bench] serving: {lam_sat:.1f} solves/s saturated; Poisson run at {rate:.1f}/s",
-          file=sys.stderr, flush=True)
-    res, info = serve_once(igmres, mdps, arr, prep_threads)
-    lat_ms = np.array([l for l, _, _ in res]) * 1e3
-    span = max(c for _, c, _ in res)
-    sts = [st for _, _, st in res]
-    assert all(st["converged"] == 1 for st in sts), "a served request did not converge"
+    assert all(st["converged"] == 1 for _, _, st in sat), "a served request did not converge"
     dev_ms = sum(st["time_ms"] for _, _, st in sat)
     alg = sum(st["alg_bytes"] for _, _, st in sat)
+    link = h2d_bandwidth(torch)
+    # Poisson arrivals at each offered load x the saturated throughput
+    at_load = {}
+    for load in loads:
+        rate = load * lam_sat
+        arr = np.array([r.arrival for r in synth.serving_stream(count, rate, seed)])
+        print(f"[bench] serving: {lam_sat:.1f} solves/s saturated; Poisson run at {rate:.1f}/s",
+              file=sys.stderr, flush=True)
+        res, _ = serve_once(igmres, mdps, arr, prep_threads)
+        lat_ms = np.array([lt for lt, _, _ in res]) * 1e3
+        span = max(c for _, c, _ in res)
+        sts = [st for _, _, st in res]
+        assert all(st["converged"] == 1 for st in sts), "a served request did not converge"
+        at_load[str(load)] = {
+            "arrival_rate_per_s": round(rate, 2), "solves_per_s": round(count / span, 2),
+            "p50_latency_ms": round(float(np.percentile(lat_ms, 50)), 3),
+            "p99_latency_ms": round(float(np.percentile(lat_ms, 99)), 3),
+            "mean_queue_ms": round(float(np.mean([st["queue_ms"] for st in sts])), 3),
+            "mean_prep_ms": round(float(np.mean([st["prep_ms"] for st in sts])), 3),
+            "mean_device_ms": round(float(np.mean([st["time_ms"] for st in sts])), 3),
+            "max_res_inf": float(max(st["res_inf"] for st in sts))}
     print("[bench] serving: sequential FP64 baseline", file=sys.stderr, flush=True)
     nseq, tseq = sequential_fp64(igmres, torch, mdps)
+    main_load = at_load.get("0.8", next(iter(at_load.values())))
     return {
         "workload": f"first {count} requests of the seeded serving stream (seed {seed}): "
                     "n log-uniform in [1e3, 2e5], m in 2..16, k in 4..32 uniform successors, "
@@ -394,16 +432,17 @@ def serving_leg(igmres, synth, torch, count, seed, load=0.8, prep_threads=4):
                     "host CSR in, V and pi back to the host",
         "requests": count, "nnz_mean": round(float(nnz.mean())), "nnz_max": int(nnz.max()),
         "saturated_solves_per_s": round(lam_sat, 2),
-        "offered_load": load, "arrival_rate_per_s": round(rate, 2),
-        "solves_per_s": round(count / span, 2),
-        "p50_latency_ms": round(float(np.percentile(lat_ms, 50)), 3),
-        "p99_latency_ms": round(float(np.percentile(lat_ms, 99)), 3),
-        "mean_queue_ms": round(float(np.mean([st["queue_ms"] for st in sts])), 3),
-        "mean_prep_ms": round(float(np.mean([st["prep_ms"] for st in sts])), 3),
-        "mean_device_ms": round(float(np.mean([st["time_ms"] for st in sts])), 3),
-        "max_res_inf": float(max(st["res_inf"] for st in sts)),
+        "offered_load": 0.8, "arrival_rate_per_s": main_load["arrival_rate_per_s"],
+        "solves_per_s": main_load["solves_per_s"],
+        "p50_latency_ms": main_load["p50_latency_ms"], "p99_latency_ms": main_load["p99_latency_ms"],
+        "at_load": at_load,
         "saturated_overlap": round(dev_ms / (makespan * 1e3), 3),
         "saturated_alg_GBps": round(alg / makespan / 1e9, 2),
+        # the link bound: every request's CSR crosses host->device once
+        "upload_MB_mean": round(float(up.mean()) / 1e6, 2),
+        "saturated_upload_GBps": round(float(up.sum()) / makespan / 1e9, 2),
+        "h2d_link_GBps": round(link, 2),
+        "link_bound_solves_per_s": round(link * 1e9 / float(up.mean()), 2),
         "peak_running": info_sat["peak_running"], "prep_threads": prep_threads,
         "arena_peak_GiB": round(info_sat["arena_peak"] / 2**30, 3),
         "sequential_fp64_solves_per_s": round(nseq / tseq, 2), "sequential_fp64_requests": nseq,

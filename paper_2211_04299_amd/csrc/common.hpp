@@ -58,9 +58,9 @@ constexpr int kMaxW = IG_MAX_RESTART;
 // sliced ELL views.  Slice b (states 64b .. 64b+63) has width K_b.
 //   full P:     entry (a, j, l) at off[b] + ((a*K_b + j) << 6) + l
 //   compact P^pi entry (j, l) at offp[b] + (j << 6) + l
-// Padding entries have column 0 and value 0.  The full P arrays carry
-// kRowPad zero entries after the last slice, so a wavefront may read 16 whole
-// slots of any row (see k_bellman).
+// Padding entries have column 0 and value 0.  The full P and the compact
+// P^pi arrays carry kRowPad zero entries after the last slice, so a
+// wavefront may read 16 whole slots of any row (see k_bellman, row_whole).
 constexpr int64_t kRowPad = 16 * 64;
 // ---------------------------------------------------------------------------
 template <typename VT>

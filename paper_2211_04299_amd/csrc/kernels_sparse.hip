@@ -40,6 +40,51 @@ __device__ __forceinline__ AT ell_row(const int32_t* __restrict__ col, const VT*
   return acc;
 }
 
+// The same sum for one lane per state and rows of K <= KR entries: all KR
+// slots are loaded from one base address (immediate offsets), so every load
+// of the row is in flight at once; slots past K read the next row or the
+// zero tail after the last slice and are not used.  Same order and rounding
+// as ell_row.
+template <typename VT, typename XT, typename AT, int KR>
+__device__ __forceinline__ AT row_whole(const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                        int64_t base, int K, const XT* __restrict__ x, XT scale) {
+  int32_t c[KR];
+  VT v[KR];
+  const int32_t* cb = col + base;
+  const VT* vb = val + base;
+#pragma unroll
+  for (int j = 0; j < KR; ++j) {
+    c[j] = ld_stream(cb + (j << 6));
+    v[j] = ld_stream(vb + (j << 6));
+  }
+  AT acc = 0;
+#pragma unroll
+  for (int h = 0; h < KR; h += KR / 2) {
+    XT xv[KR / 2];
+#pragma unroll
+    for (int j = 0; j < KR / 2; ++j) xv[j] = h + j < K ? x[c[h + j]] : (XT)0;
+#pragma unroll
+    for (int j = 0; j < KR / 2; ++j)
+      if (h + j < K) {
+        if constexpr (sizeof(AT) == 8)
+          acc = fma(to_d(v[h + j]), (AT)(xv[j] * scale), acc);
+        else
+          acc = fmaf(to_f(v[h + j]), (AT)(xv[j] * scale), acc);
+      }
+  }
+  return acc;
+}
+
+// ell_row (G lanes per state) or row_whole (KR > 0: one lane, short rows)
+template <typename VT, typename XT, typename AT, int G, int KR>
+__device__ __forceinline__ AT pi_row(const SellPi<VT>& Pp, int64_t b, int l, int g,
+                                     const XT* __restrict__ x, XT scale) {
+  if constexpr (KR > 0)
+    return row_whole<VT, XT, AT, KR>(Pp.col, Pp.val, Pp.off[b] + l, Pp.width[b], x, scale);
+  else
+    return ell_row<VT, XT, AT, G>(Pp.col, Pp.val, Pp.off[b] + l, Pp.width[b], g, x, scale);
+}
+
 template <typename AT, int G>
 __device__ __forceinline__ AT group_sum(AT acc) {
   constexpr int S = kWave / G;
@@ -214,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_bellman(
 }
 
 // y = xs - gamma * P^pi xs, xs = x * scale (scale = 1/eta, or 1)
-template <typename VT, typename XT, typename AT, int G>
+template <typename VT, typename XT, typename AT, int G, int KR>
 __global__ __launch_bounds__(kBlock) void k_japply(SellPi<VT> Pp, int64_t n, AT gamma,
                                                    const XT* __restrict__ x,
                                                    const double* __restrict__ eta,
@@ -230,8 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_japply(SellPi<VT> Pp, int64_t n, AT 
     const int64_t s = w * S + ls;
     const int64_t b = s >> 6;
     const int l = (int)(s & 63);
-    const AT acc = group_sum<AT, G>(
-        ell_row<VT, XT, AT, G>(Pp.col, Pp.val, Pp.off[b] + l, Pp.width[b], g, x, scale));
+    const AT acc = group_sum<AT, G>(pi_row<VT, XT, AT, G, KR>(Pp, b, l, g, x, scale));
     if (s < n && g == 0) {
       const XT xs = x[s] * scale;
       y[s] = (XT)((AT)xs - gamma * acc);
@@ -241,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_japply(SellPi<VT> Pp, int64_t n, AT 
 
 // One Horner step of the Neumann preconditioner M^{-1} = sum_{k<=d} (gamma
 // P^pi)^k:  y = x * sx + gamma * (P^pi z) * sz  (sx, sz = 1 / *eta or 1).
-template <typename VT, typename XT, typename AT, int G>
+template <typename VT, typename XT, typename AT, int G, int KR>
 __global__ __launch_bounds__(kBlock) void k_pstep(SellPi<VT> Pp, int64_t n, AT gamma,
                                                   const XT* __restrict__ x,
                                                   const double* __restrict__ sx,
@@ -259,15 +303,14 @@ __global__ __launch_bounds__(kBlock) void k_pstep(SellPi<VT> Pp, int64_t n, AT g
     const int64_t s = w * S + ls;
     const int64_t b = s >> 6;
     const int l = (int)(s & 63);
-    const AT acc = group_sum<AT, G>(
-        ell_row<VT, XT, AT, G>(Pp.col, Pp.val, Pp.off[b] + l, Pp.width[b], g, z, (XT)1));
+    const AT acc = group_sum<AT, G>(pi_row<VT, XT, AT, G, KR>(Pp, b, l, g, z, (XT)1));
     if (s < n && g == 0) y[s] = (XT)((AT)x[s] * ax + gamma * acc * az);
   }
 }
 
 // MODE 0: r = g^pi - (V - gamma P^pi V), partials {max|r|, ||r||^2, max|V|}
 // MODE 1: Vout = g^pi + gamma P^pi Vin, partials {max|Vout - Vin|, ||.||^2, 0}
-template <typename VT, int G, int MODE>
+template <typename VT, int G, int MODE, int KR>
 __global__ __launch_bounds__(kBlock) void k_policy_pass(SellPi<VT> Pp, int64_t n, double gamma,
                                                         const double* __restrict__ cpi,
                                                         const double* __restrict__ V,
@@ -284,8 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_pass(SellPi<VT> Pp, int64_t n
     const int64_t s = w * S + ls;
     const int64_t b = s >> 6;
     const int l = (int)(s & 63);
-    const double acc = group_sum<double, G>(
-        ell_row<VT, double, double, G>(Pp.col, Pp.val, Pp.off[b] + l, Pp.width[b], g, V, 1.0));
+    const double acc = group_sum<double, G>(pi_row<VT, double, double, G, KR>(Pp, b, l, g, V, 1.0));
     if (s < n && g == 0) {
       double v;
       if (MODE == 0) {
@@ -397,15 +439,32 @@ struct RunBellman {
   }
 };
 
+// one lane per state and rows of at most 16 entries: whole-row loads
+template <int G, typename F>
+void with_rows(const Mdp& d, F&& f) {
+  if constexpr (G == 1) {
+    if (d.maxK <= 16) {
+      f(std::integral_constant<int, 16>{});
+      return;
+    }
+  }
+  f(std::integral_constant<int, 0>{});
+}
+
 template <typename VT, int G>
 struct RunJapply {
   static void run(Mdp& d, bool fp32, const void* x, const double* eta, void* y, hipStream_t s) {
-    if (fp32)
-      hipLaunchKernelGGL((k_japply<VT, float, float, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
-                         viewPi<VT>(d), d.n, (float)d.gamma, (const float*)x, eta, (float*)y);
-    else
-      hipLaunchKernelGGL((k_japply<VT, double, double, G>), dim3(grid_for(d, G)), dim3(kBlock), 0,
-                         s, viewPi<VT>(d), d.n, d.gamma, (const double*)x, eta, (double*)y);
+    with_rows<G>(d, [&](auto kr) {
+      constexpr int KR = decltype(kr)::value;
+      if (fp32)
+        hipLaunchKernelGGL((k_japply<VT, float, float, G, KR>), dim3(grid_for(d, G)),
+                           dim3(kBlock), 0, s, viewPi<VT>(d), d.n, (float)d.gamma, (const float*)x,
+                           eta, (float*)y);
+      else
+        hipLaunchKernelGGL((k_japply<VT, double, double, G, KR>), dim3(grid_for(d, G)),
+                           dim3(kBlock), 0, s, viewPi<VT>(d), d.n, d.gamma, (const double*)x, eta,
+                           (double*)y);
+    });
   }
 };
 
@@ -413,30 +472,39 @@ template <typename VT, int G>
 struct RunPstep {
   static void run(Mdp& d, bool fp32, const void* x, const double* sx, const void* z,
                   const double* sz, void* y, hipStream_t s) {
-    if (fp32)
-      hipLaunchKernelGGL((k_pstep<VT, float, float, G>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
-                         viewPi<VT>(d), d.n, (float)d.gamma, (const float*)x, sx, (const float*)z,
-                         sz, (float*)y);
-    else
-      hipLaunchKernelGGL((k_pstep<VT, double, double, G>), dim3(grid_for(d, G)), dim3(kBlock), 0,
-                         s, viewPi<VT>(d), d.n, d.gamma, (const double*)x, sx, (const double*)z,
-                         sz, (double*)y);
+    with_rows<G>(d, [&](auto kr) {
+      constexpr int KR = decltype(kr)::value;
+      if (fp32)
+        hipLaunchKernelGGL((k_pstep<VT, float, float, G, KR>), dim3(grid_for(d, G)), dim3(kBlock),
+                           0, s, viewPi<VT>(d), d.n, (float)d.gamma, (const float*)x, sx,
+                           (const float*)z, sz, (float*)y);
+      else
+        hipLaunchKernelGGL((k_pstep<VT, double, double, G, KR>), dim3(grid_for(d, G)),
+                           dim3(kBlock), 0, s, viewPi<VT>(d), d.n, d.gamma, (const double*)x, sx,
+                           (const double*)z, sz, (double*)y);
+    });
   }
 };
 
 template <typename VT, int G>
 struct RunResidual {
   static void run(Mdp& d, const double* V, double* r, hipStream_t s) {
-    hipLaunchKernelGGL((k_policy_pass<VT, G, 0>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
-                       viewPi<VT>(d), d.n, d.gamma, (const double*)d.cpi, V, r, d.part);
+    with_rows<G>(d, [&](auto kr) {
+      hipLaunchKernelGGL((k_policy_pass<VT, G, 0, decltype(kr)::value>), dim3(grid_for(d, G)),
+                         dim3(kBlock), 0, s, viewPi<VT>(d), d.n, d.gamma, (const double*)d.cpi, V,
+                         r, d.part);
+    });
   }
 };
 
 template <typename VT, int G>
 struct RunVi {
   static void run(Mdp& d, const double* Vin, double* Vout, hipStream_t s) {
-    hipLaunchKernelGGL((k_policy_pass<VT, G, 1>), dim3(grid_for(d, G)), dim3(kBlock), 0, s,
-                       viewPi<VT>(d), d.n, d.gamma, (const double*)d.cpi, Vin, Vout, d.part);
+    with_rows<G>(d, [&](auto kr) {
+      hipLaunchKernelGGL((k_policy_pass<VT, G, 1, decltype(kr)::value>), dim3(grid_for(d, G)),
+                         dim3(kBlock), 0, s, viewPi<VT>(d), d.n, d.gamma, (const double*)d.cpi,
+                         Vin, Vout, d.part);
+    });
   }
 };
 

@@ -616,7 +616,8 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
         dmalloc(&d->val, (size_t)(tot + kRowPad) * d->vb) ||
         dmalloc(&d->off, (size_t)ns * 8) || dmalloc(&d->offp, (size_t)ns * 8) ||
         dmalloc(&d->width, (size_t)ns * 4) || dmalloc(&d->mcnt, (size_t)ns * 4) ||
-        dmalloc(&d->pcol, (size_t)totp * 4) || dmalloc(&d->pval, (size_t)totp * d->vb))
+        dmalloc(&d->pcol, (size_t)(totp + kRowPad) * 4) ||
+        dmalloc(&d->pval, (size_t)(totp + kRowPad) * d->vb))
       return IG_E_NOMEM;
     if (!dev_route) {
       if (ig_status e = upload(d, d->col, scol, (size_t)tot * 4)) return e;
@@ -706,11 +707,11 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
       G.max_stored_sum = mss;
       if (ig_status e2 = check(G)) return e2;
     }
-    if (ig_status e = dzero(d, d->pcol, (size_t)totp * 4)) return e;
-    if (ig_status e = dzero(d, d->pval, (size_t)totp * d->vb)) return e;
+    if (ig_status e = dzero(d, d->pcol, (size_t)(totp + kRowPad) * 4)) return e;
+    if (ig_status e = dzero(d, d->pval, (size_t)(totp + kRowPad) * d->vb)) return e;
     if (d->refine) {  // BF16 compact P^pi, rounded from the FP32 one per policy
-      if (dmalloc(&d->in_pval, (size_t)totp * d->in_vb)) return IG_E_NOMEM;
-      if (ig_status e = dzero(d, d->in_pval, (size_t)totp * d->in_vb)) return e;
+      if (dmalloc(&d->in_pval, (size_t)(totp + kRowPad) * d->in_vb)) return IG_E_NOMEM;
+      if (ig_status e = dzero(d, d->in_pval, (size_t)(totp + kRowPad) * d->in_vb)) return e;
     }
 
     // lanes per state: enough lanes in flight to cover latency on 256 CUs
@@ -906,8 +907,8 @@ ig_status device_footprint(const ig_mdp_desc* desc, int restart, bool fp32, size
     }
     b += round256((tot + kRowPad) * 4) + round256((tot + kRowPad) * vb) + 2 * round256(ns * 8) +
          2 * round256(ns * 4) +
-         round256(totp * 4) + round256(totp * vb);
-    if (desc->refine) b += round256(totp * 2);
+         round256((totp + kRowPad) * 4) + round256((totp + kRowPad) * vb);
+    if (desc->refine) b += round256((totp + kRowPad) * 2);
     // raw CSR staging of the device conversion: taken from the top of a
     // region after the sliced-ELL arrays (and the mask), dead once the
     // conversion is done, so the later allocations may reuse its bytes
