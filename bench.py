@@ -579,6 +579,11 @@ def main():
         roof = {"bound": "hbm" if p_bytes >= 256e6 else "latency", "achieved": round(ach, 2),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                # the measured HBM-side bytes per launch at the same duration:
+                # how close the launch runs to the peak with the bytes it moves
+                "traffic_GBps": round(traffic / (dom_avg_ms * 1e-3) / 1e9, 1) if traffic else None,
+                "traffic_frac": round(traffic / (dom_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+                if traffic else None,
                 "kernel": dom, "launches": dom_n, "avg_us": round(dom_avg_ms * 1e3, 3),
                 "alg_bytes_per_launch": b, "copy_GBps": round(cbw, 1), "regime": regime}
 
