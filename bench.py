@@ -313,8 +313,12 @@ def serving_requests(synth, count, seed):
         m = r.make(threads=1)
         m.val = m.val.astype(np.float32)
         return m
+    mdps = []
     with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
-        mdps = list(ex.map(make, specs))
+        for i, m in enumerate(ex.map(make, specs)):
+            mdps.append(m)
+            if (i + 1) % 250 == 0:
+                print(f"[bench] serving: {i + 1} of {count} requests generated", file=sys.stderr, flush=True)
     return specs, mdps
 
 
