@@ -13,12 +13,12 @@ Prints one JSON line.  Extra keys: "roofline" for the dominant kernel (HIP
 events around its launches during the timed steps; algorithmic bytes per
 launch from the kernel's definition), "cpu_baseline" (the FP64 oracle's
 literal Algorithm 2 on the host, a bounded sample of solves) and "serving"
-(continuous batching of a prefix of the serving stream: uneven sparse
+(continuous batching of the serving stream, 2000 requests: uneven sparse
 requests, n log-uniform in [1e3, 2e5], m in 2..16, k in 4..32, gamma in
 {0.9, 0.95, 0.99}, FP32-stored P, mixed precision, W = 30, tol 1e-8;
 saturated throughput with every request queued at once, then p50/p99
-latency under Poisson arrivals at 0.8x that throughput, beside the same
-requests solved one at a time by the plain FP64 path).
+latency under Poisson arrivals at 0.5, 0.8 and 1.0x that throughput, beside
+the same requests solved one at a time by the plain FP64 path).
 
 The roofline also names its regime ("regime": HBM streaming, or latency-bound
 when the stored MDP fits the 256 MB last-level cache and repeated passes
@@ -463,7 +463,9 @@ def main():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c5"])
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other single-GPU workloads (c2, c3) timed beside the main one")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the serving stream (2000: the whole stream; its CSR arrays take "
+                         "about 115 GB of host memory)")
     ap.add_argument("--prep-threads", type=int, default=4)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--precond", type=int, default=0,
