@@ -223,8 +223,14 @@ __global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, 
   XT* qc = Q + (int64_t)c * n;
   const int64_t s0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   // y and w1 of the next row are loaded one iteration ahead (index clamped
-  // into range), so that their latency overlaps the basis loads
+  // into range), so that their latency overlaps the basis loads; for rows of
+  // up to 128 bytes (32 FP32 or 16 FP64 columns) the next row of the basis
+  // is loaded ahead too (the grid keeps two wavefronts per SIMD, so the
+  // registers are there)
+  constexpr bool PF = JM * sizeof(XT) <= 128;
   XT yn = y[min(s0, n - 1)], wn = w1[min(s0, n - 1)];
+  XT qn[PF ? JM : 1];
+  if constexpr (PF) load_row<XT, JM>(Q, n, c, min(s0, n - 1), qn);
   for (int64_t s = s0; s < n; s += stride) {
     // re-read the LDS coefficients per row instead of holding 2*JM doubles
     // in registers
@@ -233,7 +239,13 @@ __global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, 
     yn = y[min(s + stride, n - 1)];
     wn = w1[min(s + stride, n - 1)];
     XT q[JM];
-    load_row<XT, JM>(Q, n, c, s, q);
+    if constexpr (PF) {
+#pragma unroll
+      for (int j = 0; j < JM; ++j) q[j] = qn[j];
+      load_row<XT, JM>(Q, n, c, min(s + stride, n - 1), qn);
+    } else {
+      load_row<XT, JM>(Q, n, c, s, q);
+    }
     const double ys = to_d(yv);
     CT corr0 = 0, corr1 = 0, r0 = 0, r1 = 0;
 #pragma unroll
@@ -286,13 +298,24 @@ __global__ __launch_bounds__(kBlock) void k_gs_b(const XT* __restrict__ Q, int64
   double nrm = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int64_t s0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  XT yn = y[min(s0, n - 1)];  // one row ahead, index clamped into range
+  // y, and for rows of up to 128 bytes the basis row, one row ahead (index
+  // clamped into range)
+  constexpr bool PF = JM * sizeof(XT) <= 128;
+  XT yn = y[min(s0, n - 1)];
+  XT qn[PF ? JM : 1];
+  if constexpr (PF) load_row<XT, JM>(Q, n, cnt, min(s0, n - 1), qn);
   for (int64_t s = s0; s < n; s += stride) {
     asm volatile("" ::: "memory");
     const XT yv = yn;
     yn = y[min(s + stride, n - 1)];
     XT q[JM];
-    load_row<XT, JM>(Q, n, cnt, s, q);
+    if constexpr (PF) {
+#pragma unroll
+      for (int j = 0; j < JM; ++j) q[j] = qn[j];
+      load_row<XT, JM>(Q, n, cnt, min(s + stride, n - 1), qn);
+    } else {
+      load_row<XT, JM>(Q, n, cnt, s, q);
+    }
     CT a0 = yv, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
     for (int g = 0; g < JM; g += 8) {
