@@ -42,7 +42,6 @@ constexpr int kPB = 1024;            // threads per block
 constexpr int kPWaves = kPB / kWave;
 constexpr int kPMaxBlocks = 256;
 constexpr int kPMaxSpb = 32;         // slices per block
-constexpr int kPMaxOwn = kPMaxSpb * kSlice;
 constexpr int kPMaxW = kPersistMaxRestart;  // restart cap of this engine (LDS Givens state)
 constexpr int kPStride = kPMaxW + 8; // doubles per block row of partials
 constexpr long kSpinLimit = 1L << 23;  // polls per barrier wait (IG_SPIN_LIMIT overrides)
@@ -696,7 +695,10 @@ __global__ __launch_bounds__(kPB) void k_persist(PArgs<VT, XT> A) {
         if (lane <= i) L.R[i * (kPMaxW + 1) + lane] = L.c[lane];
       }
       if (threadIdx.x == 0) {
-        sc.alg_bytes += A.b_japply + A.b_vec * (3.0 * (i + 1) + 4.0);
+        // the product, then the method's basis traffic for Q_0..Q_i (read
+        // twice, as modified Gram-Schmidt does) and four more vectors; the
+        // second classical pass reads the basis once more, not counted
+        sc.alg_bytes += A.b_japply + A.b_vec * (2.0 * (i + 1) + 4.0);
         const double eta = L.c[i + 1];
         const double rho = fabs(L.g[i + 1]);
         sc.eta = eta;

@@ -74,15 +74,13 @@ struct Bytes {
            (d.refine && d.fmt == IG_FMT_CSR ? nnz_pi() * (d.vb + d.in_vb) : 0.0);
   }
   double japply(bool fp32) const { return nnz_pi() * entry_in() + d.n * (fp32 ? 4.0 : 8.0) * 2; }
-  // Orthogonalisation of column c.  Fused form: pass A reads Q_0..Q_{c-1},
-  // w1 and y and writes Q_c (c = 0: reads Q_0 and y); pass B reads
-  // Q_0..Q_c and y and writes w1.  Separate form: formation (c columns + w1
-  // in, Q_c out), two projections over c+1 columns and the update.
+  // Orthogonalisation against Q_0..Q_c: the method's basis traffic (each
+  // column read twice, as modified Gram-Schmidt does) and four more vectors.
+  // The passes run here move more (the fused form reads the basis in both
+  // of its passes); that extra is an implementation cost, not counted.
   double gs(bool fp32, int c) const {
     const double xb = fp32 ? 4 : 8;
-    if (c + 1 <= gs_fused_max(fp32))
-      return d.n * xb * ((c > 0 ? c + 3.0 : 2.0) + (c + 3.0));
-    return d.n * xb * ((c + 2.0) + (c + 2.0) + (c + 3.0) + (c + 2.0));
+    return d.n * xb * (2.0 * (c + 1) + 4.0);
   }
   double update(bool fp32, int i) const { return d.n * (i * (fp32 ? 4.0 : 8.0) + 16); }
   double residual() const { return nnz_pi() * entry() + d.n * 24.0; }

@@ -60,6 +60,25 @@ def test_c4_banded_fp32_full_size():
           f"rel_error_bound={rb:.2e}")
 
 
+def test_c4_refine_full_size():
+    """BF16 P^pi inside GMRES beside the FP32 copy at n = 4e6: the outer
+    residual is the FP32-stored MDP's, so the certificate against the FP64
+    oracle's Bellman operator on that MDP holds at the mixed tolerance."""
+    I = igm()
+    mdp = synth.config("c4", seed=0)
+    ref = mdp.with_values(val=synth.upcast_values(synth.round_values(mdp.val, "fp32"), "fp32"))
+    with I.mdp_create(mdp, store="bf16", refine=True) as h:
+        assert h.info().refine == 1
+        V = zeros(mdp.n)
+        pi = zeros(mdp.n, "int32")
+        st = h.igmres_pi_solve(V, pi, I.params_default(mdp.gamma, tol=1e-8, restart=40, mode="mixed"))
+        Vh, pih = host(V), host(pi)
+    TV, pio, res = O.bellman(ref, Vh)
+    rb = check(mdp, Vh, pih, st, ref, TV, pio, res, tol=1e-8)
+    print(f"c4 bf16+fp32: outer={st['outer']} inner={st['inner']} restarts={st['restarts']} "
+          f"time_ms={st['time_ms']:.1f} rel_error_bound={rb:.2e}")
+
+
 @pytest.mark.parametrize("store", ["fp32", "bf16"])
 def test_c3_dense_full_size(store):
     mdp = synth.config("c3", seed=0)
