@@ -100,6 +100,13 @@ struct DevStatus {
 
 };
 
+// What the host needs after each Arnoldi step of the stream engine, written
+// by the step's last kernel straight into pinned host memory (so the host
+// can read it while the next product already runs on the stream).
+struct StepSnap {
+  double eta, rho, res_impl;
+};
+
 struct GivensState {
   double R[(kMaxW + 1) * kMaxW];  // column-major, leading dim kMaxW+1
   double cs[kMaxW];

@@ -111,6 +111,8 @@ struct Mdp {
   double* part = nullptr;       // reduction partials
   PCtl* pctl = nullptr;         // persistent-solve control block (device)
   PCtl* hpctl = nullptr;        // pinned host mirror
+  StepSnap* hsnap = nullptr;    // pinned; written by each Arnoldi step's Givens kernel
+  hipEvent_t ev_step = nullptr; // recorded after each Arnoldi step
   int num_cu = 0;
   int max_lds = 65536;          // LDS bytes a workgroup may use
   bool coop = false;            // cooperative launch supported
@@ -218,7 +220,7 @@ inline size_t round_alloc(size_t b) { return ((b < 8 ? 8 : b) + 255) & ~(size_t)
 // reduce the partials of the last nb-block finishing kernel into status /
 // Givens state (cnt: number of columns for FIN_DOTS / FIN_GIVENS)
 void launch_finalize(Mdp& d, FinKind kind, int nb, hipStream_t s, int cnt = 0,
-                     bool with_impl = false);
+                     bool with_impl = false, StepSnap* snap = nullptr);
 // Q_0 = r / sqrt(*l2sq); Givens state reset with g_hat = beta e_1.
 void launch_form_q0(Mdp& d, bool fp32, const double* r, const double* l2sq, hipStream_t s);
 // Q_c = (w1 - sum_{j<c} h2_j Q_j) / eta and the per-block maxima of the

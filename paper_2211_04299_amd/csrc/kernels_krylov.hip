@@ -222,27 +222,35 @@ __global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, 
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   XT* qc = Q + (int64_t)c * n;
   const int64_t s0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // Rows are visited from the last grid-sized chunk down to the first, the
+  // opposite order of pass B and of the product before this pass: the rows
+  // one pass touched last are still in the memory-side cache when the next
+  // pass starts on them.
   // y and w1 of the next row are loaded one iteration ahead (index clamped
   // into range), so that their latency overlaps the basis loads; for rows of
   // up to 128 bytes (32 FP32 or 16 FP64 columns) the next row of the basis
   // is loaded ahead too (the grid keeps two wavefronts per SIMD, so the
   // registers are there)
   constexpr bool PF = JM * sizeof(XT) <= 128;
-  XT yn = y[min(s0, n - 1)], wn = w1[min(s0, n - 1)];
+  int64_t sb = ((n + stride - 1) / stride - 1) * stride + s0;  // s0 + k*stride < n, k largest
+  if (sb >= n) sb -= stride;
+  const int64_t s1 = max<int64_t>(0, min(sb, n - 1));
+  XT yn = y[s1], wn = w1[s1];
   XT qn[PF ? JM : 1];
-  if constexpr (PF) load_row<XT, JM>(Q, n, c, min(s0, n - 1), qn);
-  for (int64_t s = s0; s < n; s += stride) {
+  if constexpr (PF) load_row<XT, JM>(Q, n, c, s1, qn);
+  for (int64_t s = sb; s >= 0; s -= stride) {
     // re-read the LDS coefficients per row instead of holding 2*JM doubles
     // in registers
     asm volatile("" ::: "memory");
     const XT yv = yn, wv = wn, q0v = Q[s];
-    yn = y[min(s + stride, n - 1)];
-    wn = w1[min(s + stride, n - 1)];
+    const int64_t sn = max<int64_t>(0, s - stride);
+    yn = y[sn];
+    wn = w1[sn];
     XT q[JM];
     if constexpr (PF) {
 #pragma unroll
       for (int j = 0; j < JM; ++j) q[j] = qn[j];
-      load_row<XT, JM>(Q, n, c, min(s + stride, n - 1), qn);
+      load_row<XT, JM>(Q, n, c, sn, qn);
     } else {
       load_row<XT, JM>(Q, n, c, s, q);
     }
@@ -406,39 +414,46 @@ __global__ __launch_bounds__(kBlock) void k_vadd(const double* __restrict__ a,
 
 // One-block finishing kernel: reduce cnt columns of per-block partials
 // (row stride `stride`) over nb blocks in a fixed order, then write the
-// result where the kind says.
+// result where the kind says.  FIN_GIVENS with snap: eta, rho and the
+// implicit residual of the step also go to the pinned host snapshot.
 __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __restrict__ part,
                                                     int nb, int cnt, int stride, unsigned maxmask,
                                                     int with_impl, DevStatus* __restrict__ st,
-                                                    GivensState* __restrict__ gs) {
+                                                    GivensState* __restrict__ gs,
+                                                    StepSnap* __restrict__ snap) {
   __shared__ double seg[16][64];
   __shared__ double red[kMaxW + 8];
-  if (with_impl) {  // implicit residual of the previous column: max over blocks
-    __shared__ double mx[kFinT / 64];
-    double a = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kFinT) a = fmax(a, part[(int64_t)b * stride + stride - 1]);
-    a = wave_max(a);
-    if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = mx[0];
-      for (int w = 1; w < kFinT / 64; ++w) t = fmax(t, mx[w]);
-      st->res_impl = t;
+  // The Givens state of the previous columns is loaded before the partials
+  // so that both are in flight together (one memory round trip).
+  const int col = cnt - 2;
+  double gcs = 0.0, gsn = 0.0, gh = 0.0, gg = 0.0;
+  if (kind == FIN_GIVENS) {
+    const int j = threadIdx.x;
+    if (j < col) {
+      gcs = gs->cs[j];
+      gsn = gs->sn[j];
     }
-    __syncthreads();
+    if (j <= col) gh = gs->h[j];
+    if (j == 0) gg = gs->g[col];
   }
-  for (int c0 = 0; c0 < cnt; c0 += 64) {
+  const double rimpl = kind == FIN_GIVENS && snap && threadIdx.x == 0 ? st->res_impl : 0.0;
+  // columns 0..cnt-1 of the partial rows, plus (with_impl) the implicit
+  // residual's max in the spare last column, reduced as column cnt
+  const int ncol = cnt + (with_impl ? 1 : 0);
+  for (int c0 = 0; c0 < ncol; c0 += 64) {
     const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const bool mx = c0 == 0 && c < 32 && ((maxmask >> c) & 1u);
+    const bool impl = with_impl && c0 + c == cnt;
+    const int pc = impl ? stride - 1 : c0 + c;
+    const bool mx = impl || (c0 == 0 && c < 32 && ((maxmask >> c) & 1u));
     double acc = 0.0;
-    if (c0 + c < cnt)
+    if (c0 + c < ncol)
       for (int b0 = q; b0 < nb; b0 += 16 * kFinBatch) {
         // a batch of loads in flight before the (ordered) accumulation
         double x[kFinBatch];
 #pragma unroll
         for (int u = 0; u < kFinBatch; ++u) {
           const int b = b0 + 16 * u;
-          x[u] = b < nb ? part[(int64_t)b * stride + c0 + c] : 0.0;
+          x[u] = b < nb ? part[(int64_t)b * stride + pc] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kFinBatch; ++u)
@@ -446,27 +461,30 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
       }
     seg[q][c] = acc;
     __syncthreads();
-    if (threadIdx.x < 64 && c0 + threadIdx.x < cnt) {
+    if (threadIdx.x < 64 && c0 + threadIdx.x < ncol) {
       double a = seg[0][threadIdx.x];
       for (int k = 1; k < 16; ++k) a = mx ? fmax(a, seg[k][threadIdx.x]) : a + seg[k][threadIdx.x];
       red[c0 + threadIdx.x] = a;
     }
     __syncthreads();
   }
+  if (with_impl && threadIdx.x == 0) st->res_impl = red[cnt];
   if (kind == FIN_GIVENS) {
     // red = [d_0..d_col, sigma]; gs->h = first-pass coefficients of column
     // col.  The state is staged in LDS so that the serial rotation sweep
     // touches no global memory.
     __shared__ double h[kMaxW + 2], cs[kMaxW + 1], sn[kMaxW + 1], z[kMaxW + 2], g2[2];
     __shared__ double eta_s;
-    const int col = cnt - 2;
-    for (int j = threadIdx.x; j < col; j += kFinT) {
-      cs[j] = gs->cs[j];
-      sn[j] = gs->sn[j];
+    {
+      const int j = threadIdx.x;
+      if (j < col) {
+        cs[j] = gcs;
+        sn[j] = gsn;
+      }
+      if (j <= col) h[j] = gh + red[j];
     }
-    for (int j = threadIdx.x; j <= col; j += kFinT) h[j] = gs->h[j] + red[j];
     if (threadIdx.x == 0) {
-      g2[0] = gs->g[col];
+      g2[0] = gg;
       double dd = 0.0;
       for (int j = 0; j <= col; ++j) dd = fma(red[j], red[j], dd);
       eta_s = sqrt(fmax(red[col + 1] - dd, 0.0));
@@ -515,6 +533,11 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
       gs->g[col + 1] = g2[1];
       st->eta = eta_s;
       st->rho = fabs(g2[1]);
+      if (snap) {  // system scope: the stores go to host memory, not the L2
+        __hip_atomic_store(&snap->eta, eta_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&snap->rho, fabs(g2[1]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&snap->res_impl, rimpl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
     return;
   }
@@ -558,7 +581,8 @@ inline int gs_grid(const Mdp& d) {  // grid-stride kernels
 
 }  // namespace
 
-void launch_finalize(Mdp& d, FinKind kind, int nb, hipStream_t s, int cnt, bool with_impl) {
+void launch_finalize(Mdp& d, FinKind kind, int nb, hipStream_t s, int cnt, bool with_impl,
+                     StepSnap* snap) {
   int stride = 0;
   unsigned mask = 0;
   switch (kind) {
@@ -571,7 +595,7 @@ void launch_finalize(Mdp& d, FinKind kind, int nb, hipStream_t s, int cnt, bool 
     case FIN_GIVENS: stride = kPartStride; mask = 0u; break;
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinT), 0, s, (int)kind, (const double*)d.part, nb,
-                     cnt, stride, mask, with_impl ? 1 : 0, d.st, d.gs);
+                     cnt, stride, mask, with_impl ? 1 : 0, d.st, d.gs, snap);
 }
 
 void launch_form_q0(Mdp& d, bool fp32, const double* r, const double* l2sq, hipStream_t s) {
@@ -608,7 +632,7 @@ void launch_dots(Mdp& d, bool fp32, int cnt, const void* v, bool givens, bool wi
                          (const double*)d.ws.Q, d.n, cnt, (const double*)v, givens ? 1 : 0, d.part);
   }
   launch_finalize(d, givens ? FIN_GIVENS : FIN_DOTS, gs_grid(d), s, givens ? cnt + 1 : cnt,
-                  with_impl);
+                  with_impl, givens ? d.hsnap : nullptr);
 }
 
 namespace {
@@ -628,7 +652,7 @@ void gs_step_typed(Mdp& d, int c, const void* y, void* w1, hipStream_t s) {
     hipLaunchKernelGGL((k_gs_b<XT, JM>), dim3(nb), dim3(kBlock), 0, s, (const XT*)d.ws.Q, d.n,
                        c + 1, (const GivensState*)d.gs, (const XT*)y, (XT*)w1, d.part);
   }
-  launch_finalize(d, FIN_GIVENS, nb, s, c + 2, false);
+  launch_finalize(d, FIN_GIVENS, nb, s, c + 2, false, d.hsnap);
 }
 
 template <typename XT>

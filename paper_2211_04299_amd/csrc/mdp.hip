@@ -313,8 +313,10 @@ void free_all(Mdp* d) {
   if (d->own_host_mirrors) {
     if (d->hst) (void)hipHostFree(d->hst);
     if (d->hpctl) (void)hipHostFree(d->hpctl);
+    if (d->hsnap) (void)hipHostFree(d->hsnap);
   }
   if (d->ev0) (void)hipEventDestroy(d->ev0);
+  if (d->ev_step) (void)hipEventDestroy(d->ev_step);
   if (d->ev1) (void)hipEventDestroy(d->ev1);
   for (auto& pool : d->prof_ev)
     for (auto& pr : pool) {
@@ -782,12 +784,15 @@ static ig_status create_impl(const ig_mdp_desc* desc, hipStream_t stream, Mdp* d
   if (ig_status e = dzero(d, d->gs, sizeof(GivensState))) return e;
   if (d->own_host_mirrors &&
       (hipHostMalloc((void**)&d->hst, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess ||
-       hipHostMalloc((void**)&d->hpctl, sizeof(PCtl), hipHostMallocDefault) != hipSuccess))
+       hipHostMalloc((void**)&d->hpctl, sizeof(PCtl), hipHostMallocDefault) != hipSuccess ||
+       hipHostMalloc((void**)&d->hsnap, sizeof(StepSnap), hipHostMallocDefault) != hipSuccess))
     return fail(IG_E_NOMEM, "hipHostMalloc failed");
   if (ig_status e = dzero(d, d->pctl, sizeof(PCtl))) return e;
   if (d->hst) std::memset(d->hst, 0, sizeof(DevStatus));
+  if (d->hsnap) std::memset(d->hsnap, 0, sizeof(StepSnap));
   IG_HIP(hipEventCreate(&d->ev0));
   IG_HIP(hipEventCreate(&d->ev1));
+  IG_HIP(hipEventCreateWithFlags(&d->ev_step, hipEventDisableTiming));
   IG_HIP(hipGetDevice(&d->device));
   int coop = 0;
   IG_HIP(hipDeviceGetAttribute(&d->num_cu, hipDeviceAttributeMultiprocessorCount, d->device));

@@ -123,7 +123,6 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
       k_pstep(d, f32, pi, src, sc, a, nullptr, b, s);
       std::swap(a, b);
     }
-    out.bytes += precond * B.japply(f32);
     return a;
   };
   out.res_inf = r_inf;
@@ -166,6 +165,7 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
     } else {  // V = Vb + M^{-1} (Q y), the products in FP64
       launch_update(d, fp32, cnt, nullptr, V, s);
       launch_vadd(d, ws.Vb, (const double*)minv(false, V, nullptr), V, s);
+      out.bytes += precond * B.japply(false);
     }
     k_residual(d, pi, V, ws.r, s);
     out.bytes += B.update(fp32, cnt) + B.residual();
@@ -175,59 +175,94 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
     return IG_OK;
   };
 
-  for (int c = 0;;) {
+  // y = J M^{-1} (column c's input): Q_0 at c = 0, else w1 / eta
+  auto product = [&](int c) {
     if (precond > 0)
       k_japply(d, fp32, pi, minv(fp32, c == 0 ? ws.Q : w1, c == 0 ? nullptr : eta_dev), nullptr, y, s);
     else if (c == 0)
       k_japply(d, fp32, pi, ws.Q, nullptr, y, s);
     else
       k_japply(d, fp32, pi, w1, eta_dev, y, s);
+  };
+  // The product of column c+1 reads only w1 and eta of column c and writes
+  // only y, which nothing reads until the next Gram-Schmidt pass.  It is
+  // queued before the host waits for column c's scalars, so the device
+  // does not idle while the host decides; when the decision ends the cycle
+  // or the solve, the queued product is simply not used.  The scalars come
+  // from the pinned snapshot the Givens kernel writes.
+  const bool pipe = d.hsnap != nullptr && d.ev_step != nullptr;
+  bool queued = false;  // the product of column c is already on the stream
+  auto leave = [&](ig_status e) {
+    if (queued) (void)hipStreamSynchronize(s);
+    return e;
+  };
+  for (int c = 0;;) {
+    if (!queued) product(c);
+    queued = false;
     launch_gs_step(d, fp32, c, y, w1, s);
-    out.bytes += B.japply(fp32) + B.gs(fp32, c);
-    if (ig_status e = sync_status(d, s)) return e;
+    out.bytes += (1 + precond) * B.japply(fp32) + B.gs(fp32, c);
+    double eta, rho, res_impl;
+    if (pipe) {
+      IG_HIP(hipEventRecord(d.ev_step, s));
+      if (c + 1 < W && out.steps + 1 < max_inner) {
+        product(c + 1);
+        queued = true;
+      }
+      IG_HIP(hipEventSynchronize(d.ev_step));
+      const volatile StepSnap* sn = d.hsnap;
+      eta = sn->eta;
+      rho = sn->rho;
+      res_impl = sn->res_impl;
+    } else {
+      if (ig_status e = sync_status(d, s)) return e;
+      eta = d.hst->eta;
+      rho = d.hst->rho;
+      res_impl = d.hst->res_impl;
+    }
     ++out.steps;
-    const double eta = d.hst->eta, rho = d.hst->rho;
-    if (!std::isfinite(eta) || !std::isfinite(rho) || (c > 0 && !std::isfinite(d.hst->res_impl)))
-      return fail(IG_E_NUMERIC, "non-finite value in the Arnoldi process");
+    if (!std::isfinite(eta) || !std::isfinite(rho) || (c > 0 && !std::isfinite(res_impl)))
+      return leave(fail(IG_E_NUMERIC, "non-finite value in the Arnoldi process"));
     // the test of Algorithm 2 for column c-1 (residual known one step late)
-    if (c > 0 && d.hst->res_impl <= thr) {
-      if (ig_status e = explicit_residual(c)) return e;
+    if (c > 0 && res_impl <= thr) {
+      if (ig_status e = explicit_residual(c)) return leave(e);
       if (out.res_inf <= thr) {  // column c was speculative: not counted
         --out.steps;
         out.met = true;
-        return IG_OK;
+        return leave(IG_OK);
       }
       if (d.refine) {
         // refine mode: the BF16 system's residual meets the rule, the FP32
         // one does not; the next cycle solves for the correction from the
         // true residual (column c is dropped)
         --out.steps;
-        if (ig_status e = restart()) return e;
-        if (stop) return IG_OK;
+        if (ig_status e = restart()) return leave(e);
+        queued = false;
+        if (stop) return leave(IG_OK);
         c = 0;
         continue;
       }
     }
     if (eta == 0.0) {  // ||q||_2 = 0: the least-squares solution is exact; leave the loop
       ++out.breakdowns;
-      if (ig_status e = explicit_residual(c + 1)) return e;
+      if (ig_status e = explicit_residual(c + 1)) return leave(e);
       out.met = out.res_inf <= thr;
-      return IG_OK;
+      return leave(IG_OK);
     }
     // ||r||_inf <= ||r||_2 = rho: the rule holds for column c in exact arithmetic
     if (rho <= thr || out.steps >= max_inner || c + 1 == W) {
-      if (ig_status e = explicit_residual(c + 1)) return e;
+      if (ig_status e = explicit_residual(c + 1)) return leave(e);
       if (out.res_inf <= thr) {
         out.met = true;
-        return IG_OK;
+        return leave(IG_OK);
       }
-      if (out.steps >= max_inner) return IG_OK;
+      if (out.steps >= max_inner) return leave(IG_OK);
     }
     // restart from the residual at the current iterate at the end of a
     // cycle, and in refine mode after any explicit residual that missed
     if (c + 1 == W || (d.refine && rho <= thr)) {
-      if (ig_status e = restart()) return e;
-      if (stop) return IG_OK;
+      if (ig_status e = restart()) return leave(e);
+      queued = false;
+      if (stop) return leave(IG_OK);
       c = 0;
       continue;
     }
