@@ -192,6 +192,11 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
   // from the pinned snapshot the Givens kernel writes.
   const bool pipe = d.hsnap != nullptr && d.ev_step != nullptr;
   bool queued = false;  // the product of column c is already on the stream
+  // 2-norm residual of the last finished column and the infinity- to 2-norm
+  // ratio of the residual before it (negative: not known yet); they tell
+  // when the step now running will likely end the inner solve, and then the
+  // next product is not queued (it would be thrown away)
+  double last_rho = -1.0, inf_ratio = -1.0;
   auto leave = [&](ig_status e) {
     if (queued) (void)hipStreamSynchronize(s);
     return e;
@@ -204,7 +209,11 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
     double eta, rho, res_impl;
     if (pipe) {
       IG_HIP(hipEventRecord(d.ev_step, s));
-      if (c + 1 < W && out.steps + 1 < max_inner) {
+      // the step's test is on the residual of column c-1, whose 2-norm is
+      // last_rho; its infinity norm is estimated with the last ratio
+      const bool near_stop =
+          c > 0 && last_rho >= 0.0 && last_rho * (inf_ratio >= 0.0 ? inf_ratio : 1.0) <= 2.0 * thr;
+      if (c + 1 < W && out.steps + 1 < max_inner && !near_stop) {
         product(c + 1);
         queued = true;
       }
@@ -220,6 +229,8 @@ ig_status gmres_inner(Mdp& d, const int32_t* pi, double* V, double r_inf, double
       res_impl = d.hst->res_impl;
     }
     ++out.steps;
+    if (c > 0 && last_rho > 0.0) inf_ratio = res_impl / last_rho;
+    last_rho = rho;
     if (!std::isfinite(eta) || !std::isfinite(rho) || (c > 0 && !std::isfinite(res_impl)))
       return leave(fail(IG_E_NUMERIC, "non-finite value in the Arnoldi process"));
     // the test of Algorithm 2 for column c-1 (residual known one step late)
