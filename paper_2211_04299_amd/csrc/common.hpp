@@ -97,7 +97,8 @@ struct DevStatus {
   double res_impl;    // ||Q z||_inf: residual of the previous column's iterate
   int32_t nonfinite;  // NaN/Inf seen in the last Bellman pass
   int32_t changes;    // policy entries changed by the last improvement
-
+  uint32_t arrive;    // blocks of the running Gram-Schmidt pass that finished (reset by the last)
+  uint32_t pad_;
 };
 
 // What the host needs after each Arnoldi step of the stream engine, written
@@ -152,10 +153,10 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// op: 0 = sum, 1 = max.  Result valid in thread 0.
-template <int NV>
+// op: 0 = sum, 1 = max.  Result valid in thread 0.  NT: threads per block.
+template <int NV, int NT = kBlock>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV]) {
-  __shared__ double sh[NV][kBlock / kWave];
+  __shared__ double sh[NV][NT / kWave];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = op[k] ? wave_max(v[k]) : wave_sum(v[k]);
@@ -168,7 +169,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double a = sh[k][0];
-      for (int w = 1; w < kBlock / kWave; ++w) a = op[k] ? fmax(a, sh[k][w]) : a + sh[k][w];
+      for (int w = 1; w < NT / kWave; ++w) a = op[k] ? fmax(a, sh[k][w]) : a + sh[k][w];
       v[k] = a;
     }
   }

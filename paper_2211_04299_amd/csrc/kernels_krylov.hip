@@ -26,6 +26,8 @@ namespace {
 
 constexpr int kJC = 8;       // dot products per sweep
 constexpr int kFinT = 1024;  // threads of the finishing kernel
+constexpr int kGsT = 512;    // threads per block of the fused Gram-Schmidt passes
+constexpr int kGsB = 256;    // their grid cap (as many threads as 512 blocks of 256)
 constexpr int kFinBatch = 16;  // partial rows each finishing thread loads at once
 
 template <typename XT>
@@ -153,6 +155,29 @@ __global__ __launch_bounds__(kBlock) void k_form_qi(XT* __restrict__ Q, int64_t 
   if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartStride + kPartStride - 1] = v[0];
 }
 
+template <int NT>
+__device__ void finish(int kind, const double* __restrict__ part, int nb, int cnt, int stride,
+                       unsigned maxmask, int with_impl, DevStatus* __restrict__ st,
+                       GivensState* __restrict__ gs, StepSnap* __restrict__ snap);
+
+// True (uniformly in the block) for the block of the grid that finishes
+// last.  Thread 0 has written the block's partial row; its arrival is an
+// acquire-release increment of the counter, so the last block sees every
+// row.  The last block resets the counter for the next launch.
+__device__ __forceinline__ bool last_to_finish(uint32_t* arrive) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = old == gridDim.x - 1;
+    if (s_last) __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
 // ---- fused Gram-Schmidt step: two passes over the basis per column -------
 // Every thread owns one state row at a time and keeps that row of the basis
 // (at most JM columns) in registers, so each pass reads the basis once.
@@ -161,9 +186,11 @@ __global__ __launch_bounds__(kBlock) void k_form_qi(XT* __restrict__ Q, int64_t 
 //     (at c = 0 only h_0 = <Q_0, y>)
 //   pass B: w1 = y - sum_{j<=c} h_j Q_j, d_j = <Q_j, w1>, sigma = ||w1||^2
 // Partials: per block, columns 0..cnt-1 (+ sigma at cnt for B; the implicit
-// residual's max in the spare last column for A).
+// residual's max in the spare last column for A).  The block that finishes
+// last reduces them (no separate finishing launch): 512-thread blocks, at
+// most 256 of them, so that one block sums the rows in two rounds of loads.
 
-template <int JM>
+template <int JM, int NT>
 __device__ __forceinline__ void store_cols(double (&acc)[JM], int cnt, double* mypart) {
   constexpr int op8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -172,7 +199,7 @@ __device__ __forceinline__ void store_cols(double (&acc)[JM], int cnt, double* m
     double t[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) t[k] = acc[j0 + k];
-    block_reduce<8>(t, op8);
+    block_reduce<8, NT>(t, op8);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int k = 0; k < 8; ++k)
@@ -197,18 +224,18 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
 
 template <typename XT, int JM>
-__global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, int c,
+__global__ __launch_bounds__(kGsT) void k_gs_a(XT* __restrict__ Q, int64_t n, int c,
                                                  const XT* __restrict__ w1,
                                                  const XT* __restrict__ y,
-                                                 const GivensState* __restrict__ gs,
-                                                 const DevStatus* __restrict__ st,
+                                                 GivensState* __restrict__ gs,
+                                                 DevStatus* __restrict__ st,
                                                  double* __restrict__ part) {
   // The second-pass correction and the implicit residual accumulate in the
   // basis type: with an FP32 basis their rounding is that of the stored
   // vector they feed (the dot products below stay FP64).
   using CT = XT;
   __shared__ CT dd[JM], zz[JM];
-  for (int j = threadIdx.x; j < JM; j += kBlock) {
+  for (int j = threadIdx.x; j < JM; j += kGsT) {
     dd[j] = (CT)(j < c ? gs->h2[j] : 0.0);
     zz[j] = (CT)(j < c ? gs->z[j] : 0.0);
   }
@@ -219,9 +246,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, 
 #pragma unroll
   for (int j = 0; j < JM; ++j) acc[j] = 0.0;
   double accc = 0.0, rmax = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t stride = (int64_t)gridDim.x * kGsT;
   XT* qc = Q + (int64_t)c * n;
-  const int64_t s0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * kGsT + threadIdx.x;
   // Rows are visited from the last grid-sized chunk down to the first, the
   // opposite order of pass B and of the product before this pass: the rows
   // one pass touched last are still in the memory-side cache when the next
@@ -280,32 +307,37 @@ __global__ __launch_bounds__(kBlock) void k_gs_a(XT* __restrict__ Q, int64_t n, 
   for (int j = 0; j < JM; ++j)
     if (j == c) acc[j] = accc;
   double* mypart = part + (int64_t)blockIdx.x * kPartStride;
-  store_cols<JM>(acc, c + 1, mypart);
+  store_cols<JM, kGsT>(acc, c + 1, mypart);
   if (c > 0) {
     double v[1] = {rmax};
     const int op[1] = {1};
-    block_reduce<1>(v, op);
+    block_reduce<1, kGsT>(v, op);
     if (threadIdx.x == 0) mypart[kPartStride - 1] = v[0];
   }
+  // the block that finishes last reduces h (and the implicit residual)
+  if (last_to_finish(&st->arrive))
+    finish<kGsT>(FIN_DOTS, part, gridDim.x, c + 1, kPartStride, 0u, c > 0, st, gs, nullptr);
 }
 
 template <typename XT, int JM>
-__global__ __launch_bounds__(kBlock) void k_gs_b(const XT* __restrict__ Q, int64_t n, int cnt,
-                                                 const GivensState* __restrict__ gs,
+__global__ __launch_bounds__(kGsT) void k_gs_b(const XT* __restrict__ Q, int64_t n, int cnt,
+                                                 GivensState* __restrict__ gs,
+                                                 DevStatus* __restrict__ st,
                                                  const XT* __restrict__ y, XT* __restrict__ w1,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part,
+                                                 StepSnap* __restrict__ snap) {
   // w1 accumulates in the basis type (the vector is stored in it); the dot
   // products and the norm stay FP64
   using CT = XT;
   __shared__ CT h[JM];
-  for (int j = threadIdx.x; j < JM; j += kBlock) h[j] = (CT)(j < cnt ? -gs->h[j] : 0.0);
+  for (int j = threadIdx.x; j < JM; j += kGsT) h[j] = (CT)(j < cnt ? -gs->h[j] : 0.0);
   __syncthreads();
   double acc[JM];
 #pragma unroll
   for (int j = 0; j < JM; ++j) acc[j] = 0.0;
   double nrm = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const int64_t s0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kGsT;
+  const int64_t s0 = (int64_t)blockIdx.x * kGsT + threadIdx.x;
   // y, and for rows of up to 128 bytes the basis row, one row ahead (index
   // clamped into range)
   constexpr bool PF = JM * sizeof(XT) <= 128;
@@ -344,11 +376,14 @@ __global__ __launch_bounds__(kBlock) void k_gs_b(const XT* __restrict__ Q, int64
     nrm = fma(wd, wd, nrm);
   }
   double* mypart = part + (int64_t)blockIdx.x * kPartStride;
-  store_cols<JM>(acc, cnt, mypart);
+  store_cols<JM, kGsT>(acc, cnt, mypart);
   double v[1] = {nrm};
   const int op[1] = {0};
-  block_reduce<1>(v, op);
+  block_reduce<1, kGsT>(v, op);
   if (threadIdx.x == 0) mypart[cnt] = v[0];
+  // the block that finishes last runs the Givens update of the column
+  if (last_to_finish(&st->arrive))
+    finish<kGsT>(FIN_GIVENS, part, gridDim.x, cnt + 1, kPartStride, 0u, 0, st, gs, snap);
 }
 
 // Q_0 = r / beta, beta = sqrt(*l2sq); Givens state reset (block 0).
@@ -412,16 +447,18 @@ __global__ __launch_bounds__(kBlock) void k_vadd(const double* __restrict__ a,
     out[s] = a[s] + b[s];
 }
 
-// One-block finishing kernel: reduce cnt columns of per-block partials
-// (row stride `stride`) over nb blocks in a fixed order, then write the
-// result where the kind says.  FIN_GIVENS with snap: eta, rho and the
-// implicit residual of the step also go to the pinned host snapshot.
-__global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __restrict__ part,
-                                                    int nb, int cnt, int stride, unsigned maxmask,
-                                                    int with_impl, DevStatus* __restrict__ st,
-                                                    GivensState* __restrict__ gs,
-                                                    StepSnap* __restrict__ snap) {
-  __shared__ double seg[16][64];
+// Finishing work of a reduction, run by one block of NT threads: reduce cnt
+// columns of per-block partials (row stride `stride`) over nb blocks in a
+// fixed order, then write the result where the kind says.  FIN_GIVENS with
+// snap: eta, rho and the implicit residual of the step also go to the
+// pinned host snapshot.  Run by the one-block k_finalize, or by the block
+// of a Gram-Schmidt pass that finishes last.
+template <int NT>
+__device__ void finish(int kind, const double* __restrict__ part, int nb, int cnt, int stride,
+                       unsigned maxmask, int with_impl, DevStatus* __restrict__ st,
+                       GivensState* __restrict__ gs, StepSnap* __restrict__ snap) {
+  constexpr int NQ = NT / 64;  // row groups
+  __shared__ double seg[NQ][64];
   __shared__ double red[kMaxW + 8];
   // The Givens state of the previous columns is loaded before the partials
   // so that both are in flight together (one memory round trip).
@@ -447,23 +484,23 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
     const bool mx = impl || (c0 == 0 && c < 32 && ((maxmask >> c) & 1u));
     double acc = 0.0;
     if (c0 + c < ncol)
-      for (int b0 = q; b0 < nb; b0 += 16 * kFinBatch) {
+      for (int b0 = q; b0 < nb; b0 += NQ * kFinBatch) {
         // a batch of loads in flight before the (ordered) accumulation
         double x[kFinBatch];
 #pragma unroll
         for (int u = 0; u < kFinBatch; ++u) {
-          const int b = b0 + 16 * u;
+          const int b = b0 + NQ * u;
           x[u] = b < nb ? part[(int64_t)b * stride + pc] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kFinBatch; ++u)
-          if (b0 + 16 * u < nb) acc = mx ? fmax(acc, x[u]) : acc + x[u];
+          if (b0 + NQ * u < nb) acc = mx ? fmax(acc, x[u]) : acc + x[u];
       }
     seg[q][c] = acc;
     __syncthreads();
     if (threadIdx.x < 64 && c0 + threadIdx.x < ncol) {
       double a = seg[0][threadIdx.x];
-      for (int k = 1; k < 16; ++k) a = mx ? fmax(a, seg[k][threadIdx.x]) : a + seg[k][threadIdx.x];
+      for (int k = 1; k < NQ; ++k) a = mx ? fmax(a, seg[k][threadIdx.x]) : a + seg[k][threadIdx.x];
       red[c0 + threadIdx.x] = a;
     }
     __syncthreads();
@@ -519,12 +556,12 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
       z[0] = v;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j <= col; j += kFinT) {
+    for (int j = threadIdx.x; j <= col; j += NT) {
       gs->h2[j] = red[j];
       gs->h[j] = h[j];
       gs->R[(int64_t)col * (kMaxW + 1) + j] = h[j];
     }
-    for (int j = threadIdx.x; j <= col + 1; j += kFinT) gs->z[j] = z[j];
+    for (int j = threadIdx.x; j <= col + 1; j += NT) gs->z[j] = z[j];
     if (threadIdx.x == 0) {
       gs->h[col + 1] = 0.0;
       gs->cs[col] = cs[col];
@@ -542,7 +579,7 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
     return;
   }
   if (kind == FIN_DOTS) {
-    for (int j = threadIdx.x; j < cnt; j += kFinT) gs->h[j] = red[j];
+    for (int j = threadIdx.x; j < cnt; j += NT) gs->h[j] = red[j];
     return;
   }
   if (threadIdx.x != 0) return;
@@ -571,6 +608,14 @@ __global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __re
     default:
       break;
   }
+}
+
+__global__ __launch_bounds__(kFinT) void k_finalize(int kind, const double* __restrict__ part,
+                                                    int nb, int cnt, int stride, unsigned maxmask,
+                                                    int with_impl, DevStatus* __restrict__ st,
+                                                    GivensState* __restrict__ gs,
+                                                    StepSnap* __restrict__ snap) {
+  finish<kFinT>(kind, part, nb, cnt, stride, maxmask, with_impl, st, gs, snap);
 }
 
 inline int gs_grid(const Mdp& d) {  // grid-stride kernels
@@ -639,20 +684,13 @@ namespace {
 
 template <typename XT, int JM>
 void gs_step_typed(Mdp& d, int c, const void* y, void* w1, hipStream_t s) {
-  const int nb = gs_grid(d);
-  {
-    ProfScope p(d, KC_GS, s);
-    hipLaunchKernelGGL((k_gs_a<XT, JM>), dim3(nb), dim3(kBlock), 0, s, (XT*)d.ws.Q, d.n, c,
-                       (const XT*)w1, (const XT*)y, (const GivensState*)d.gs,
-                       (const DevStatus*)d.st, d.part);
-  }
-  launch_finalize(d, FIN_DOTS, nb, s, c + 1, c > 0);
-  {
-    ProfScope p(d, KC_GS, s);
-    hipLaunchKernelGGL((k_gs_b<XT, JM>), dim3(nb), dim3(kBlock), 0, s, (const XT*)d.ws.Q, d.n,
-                       c + 1, (const GivensState*)d.gs, (const XT*)y, (XT*)w1, d.part);
-  }
-  launch_finalize(d, FIN_GIVENS, nb, s, c + 2, false, d.hsnap);
+  const int64_t blocks = (d.n + kGsT - 1) / kGsT;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, kGsB));
+  ProfScope p(d, KC_GS, s);
+  hipLaunchKernelGGL((k_gs_a<XT, JM>), dim3(nb), dim3(kGsT), 0, s, (XT*)d.ws.Q, d.n, c,
+                     (const XT*)w1, (const XT*)y, d.gs, d.st, d.part);
+  hipLaunchKernelGGL((k_gs_b<XT, JM>), dim3(nb), dim3(kGsT), 0, s, (const XT*)d.ws.Q, d.n, c + 1,
+                     d.gs, d.st, (const XT*)y, (XT*)w1, d.part, d.hsnap);
 }
 
 template <typename XT>
