@@ -392,7 +392,7 @@ def request_upload_bytes(m):
     return 8 * (R + 1) + m.nnz * (4 + 4) + 8 * R
 
 
-def serving_leg(igmres, synth, torch, count, seed, loads=(0.5, 0.8, 1.0), prep_threads=4):
+def serving_leg(igmres, synth, torch, count, seed, loads=(0.5, 0.8, 1.0), prep_threads=12):
     print(f"[bench] serving: generating {count} requests", file=sys.stderr, flush=True)
     specs, mdps = serving_requests(synth, count, seed)
     nnz = np.array([m.nnz for m in mdps], dtype=np.float64)
@@ -466,7 +466,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving stream (2000: the whole stream; its CSR arrays take "
                          "about 115 GB of host memory)")
-    ap.add_argument("--prep-threads", type=int, default=4)
+    ap.add_argument("--prep-threads", type=int, default=12)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--precond", type=int, default=0,
                     help="degree of the Neumann right preconditioner of the inner GMRES (stream engine)")
