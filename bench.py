@@ -32,7 +32,9 @@ OPI with 20 sweeps (FP64 workloads) or with FP64 storage and arithmetic
 (mixed workloads), each timed from V0 = 0 to the same tolerance.  Under
 "extra" the other single-GPU workloads are timed in the same run (c2 with
 its PI and OPI comparisons; c3 with FP32, BF16 and BF16 + FP32 refinement
-storage against FP64), and "cpu_baseline" carries the oracle's times on one
+storage against FP64), under "preconditioned" (c4) the same solve with the
+truncated-Neumann right preconditioner of degree 1 and 3 in the inner GMRES
+(the paper's future work, not the headline method), and "cpu_baseline" carries the oracle's times on one
 host core and on all of them, with the host's CPU model and core count, plus
 the oracle's PI with LU evaluation, value iteration and Algorithm 2 on c2.
 
@@ -594,6 +596,22 @@ def main():
                 "alg_bytes_per_launch": b, "copy_GBps": round(cbw, 1), "regime": regime}
 
     dev_ms = np.array([s["time_ms"] for s in stats])
+    # the same workload with the truncated-Neumann right preconditioner in
+    # the inner GMRES (the paper's future work; not the headline method)
+    precond_leg = None
+    if not args.no_extra and args.workload == "c4" and args.precond == 0:
+        print("[bench] preconditioned c4", file=sys.stderr, flush=True)
+        V_main = V.clone()
+        precond_leg = {}
+        for deg in (1, 3):
+            pp = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8, mode=wl["mode"],
+                                       precond=deg)
+            timed_solves(h, h.igmres_pi_solve, V, pi, pp, 1, torch)
+            r = timed_solves(h, h.igmres_pi_solve, V, pi, pp, 3, torch)
+            r["speedup_vs_plain"] = round(ms_step / r["ms_p50"], 3)
+            r["rel_diff_vs_plain"] = float((V - V_main).abs().max() / V_main.abs().max())
+            precond_leg[f"neumann_degree_{deg}"] = r
+        V.copy_(V_main)
     cmp = None
     if not args.no_compare:
         print("[bench] comparisons", file=sys.stderr, flush=True)
@@ -646,6 +664,7 @@ def main():
         "solve_ms_p90": round(float(np.percentile(dev_ms, 90)), 4),
         "create_ms": round(create_ms, 2),
         "compare": cmp,
+        "preconditioned": precond_leg,
         "solve": {"outer": st["outer"], "inner": st["inner"], "restarts": st["restarts"],
                   "explicit_residuals": st["explicit_residuals"], "res_inf": st["res_inf"],
                   "device_ms": round(st["time_ms"], 4),
