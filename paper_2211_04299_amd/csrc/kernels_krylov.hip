@@ -17,7 +17,11 @@
 // residual rotated back to basis coordinates), whose infinity-norm equals the
 // true residual's in exact arithmetic.
 // Every dot product and norm accumulates in FP64; per-block partials are
-// combined by the one-block k_finalize in a fixed order.
+// combined in a fixed order by one block: in the fused passes (k_gs_a,
+// k_gs_b) the block that finishes last, otherwise the one-block k_finalize
+// launched next.  (The lines above name the separate kernels of the path
+// for columns beyond the register buckets; the fused passes do the same
+// work in two launches.)
 #include "internal.hpp"
 
 namespace ig {
