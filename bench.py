@@ -100,14 +100,16 @@ def kernel_group(dom, fmt):
 def per_launch_bytes(info, cls, fp32):
     """Algorithmic bytes one launch of a kernel class must move."""
     idx = 4 if info.fmt == 0 else 0
-    entry = (8 if info.store == 0 else 4 if info.store == 1 else 2) + idx
+    refine = getattr(info, "refine", 0)
+    # refine mode: the Bellman pass and residuals read the FP32 copy
+    entry = (8 if info.store == 0 else 4 if (info.store == 1 or refine) else 2) + idx
     n, m = info.n, info.m
     xb = 4 if fp32 else 8
     nnz_pi = info.nnz / m
     if cls == "bellman":  # P (all actions), g, V; Phi, pi and g^pi out
         return info.nnz * entry + n * m * 8 + n * 8 + n * (8 + 4 + 8)
     if cls == "japply":   # P^pi (the BF16 copy in refine mode), x in, y out
-        return nnz_pi * ((2 + idx) if getattr(info, "refine", 0) else entry) + n * xb * 2
+        return nnz_pi * ((2 + idx) if refine else entry) + n * xb * 2
     if cls == "residual":
         return nnz_pi * entry + n * 8 * 3
     return None  # classes whose bytes depend on the step (persistent, Gram-Schmidt)
@@ -259,6 +261,31 @@ def cpu_baseline(mdp, restart, synth=None, wl_cfg=None, seed=0, budget_s=8.0, c2
     return out
 
 
+def class_rooflines(igmres, torch, h, V, pi, params, fp32, runs=3):
+    """Average launch time of the streaming kernel classes over `runs`
+    solves (HIP events on the launch stream) and their algorithmic bytes per
+    launch over that time, against the HBM peak."""
+    info = h.info()
+    h.profile_enable((1 << igmres.IG_PROFILE_CLASSES) - 1)
+    for _ in range(runs):
+        V.zero_()
+        h.igmres_pi_solve(V, pi, params)
+    torch.cuda.synchronize()
+    prof = h.profile_read(reset=True)
+    h.profile_enable(0)
+    out = {}
+    for cls in ("bellman", "japply", "residual"):
+        ms, cnt = prof.get(cls, (0.0, 0))
+        b = per_launch_bytes(info, cls, fp32)
+        if not cnt or not b:
+            continue
+        avg = ms / cnt
+        gbps = b / (avg * 1e-3) / 1e9
+        out[cls] = {"avg_us": round(avg * 1e3, 2), "alg_bytes_per_launch": round(b),
+                    "achieved_GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+    return out
+
+
 def extra_leg(igmres, synth, torch, name, seed):
     """Another single-GPU workload timed in the same run: c2 (FP64,
     persistent engine) with exact-evaluation PI and OPI(20) beside it; c3
@@ -291,6 +318,7 @@ def extra_leg(igmres, synth, torch, name, seed):
             p = igmres.params_default(mdp.gamma, restart=restart, tol=1e-8, mode=mode)
             timed_solves(h, h.igmres_pi_solve, V, pi, p, 3, torch)
             r = timed_solves(h, h.igmres_pi_solve, V, pi, p, 20, torch)
+            r["kernels"] = class_rooflines(igmres, torch, h, V, pi, p, mode == "mixed")
         Vh = V.double().cpu()
         if ref is None:
             ref = Vh
