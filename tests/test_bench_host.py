@@ -28,6 +28,12 @@ def test_algorithmic_bytes_sparse_and_dense():
     # refine mode: the products read the BF16 copy of P^pi
     refine = SimpleNamespace(n=n, m=m, nnz=n * m * k, store=1, fmt=0, refine=1)
     assert bench.per_launch_bytes(refine, "japply", True) == n * k * 6 + n * 4 * 2
+    # a refine handle stores BF16 for the products and keeps an FP32 copy, which
+    # the Bellman pass and the residuals read
+    refine16 = SimpleNamespace(n=n, m=m, nnz=n * m * k, store=2, fmt=0, refine=1)
+    assert bench.per_launch_bytes(refine16, "japply", True) == n * k * 6 + n * 4 * 2
+    assert bench.per_launch_bytes(refine16, "bellman", True) == n * m * k * 8 + n * m * 8 + n * 8 + n * 20
+    assert bench.per_launch_bytes(refine16, "residual", True) == n * k * 8 + n * 24
     assert bench.per_launch_bytes(sparse, "residual", False) == n * k * 12 + n * 24
     dense = SimpleNamespace(n=n, m=4, nnz=n * 4 * n, store=2, fmt=1)  # BF16 rows, no column indices
     assert bench.per_launch_bytes(dense, "bellman", True) == n * 4 * n * 2 + n * 4 * 8 + n * 8 + n * 20
