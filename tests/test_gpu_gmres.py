@@ -90,3 +90,46 @@ def test_eval_rejects_bad_policy():
             h.policy_eval_gmres(dev_vec(pi, "int32"), dev_vec(np.zeros(100)),
                                 I.params_default(0.9))
         assert e.value.status == I.IG_E_INVALID
+
+
+def test_eval_matches_literal_algorithm_past_one_grid_stride():
+    """n = 140003 is more rows than the Gram-Schmidt passes have threads
+    (256 blocks of 512), so some threads take a second row and the last rows
+    form a ragged tail; 54 steps with W = 36 run past the 32 columns the fused
+    FP64 passes hold (later columns take the separate projection kernels).
+    Same stopping step, restarts and iterate as the literal algorithm."""
+    n, W, alpha = 140003, 36, 1e-4
+    mdp = synth.sparse_band(n, 2, 8, 0.995, seed=5)
+    pi = np.random.default_rng(5).integers(0, 2, size=n).astype(np.int32)
+    x0 = np.zeros(n)
+    Vg, st = gpu_eval(mdp, pi, x0, alpha, W)
+    Vo, info = O.gmres_inner(mdp, pi, x0, alpha, W)
+    print(f"fp64 n={n}: inner={st['inner']} restarts={st['restarts']} oracle steps={info['steps']}")
+    assert info["steps"] > 32 and info["restarts"] >= 1
+    assert st["status"] == 0 and st["converged"] == 1
+    assert st["inner"] == info["steps"], (st, info["steps"])
+    assert st["restarts"] == info["restarts"]
+    scale = max(1.0, np.max(np.abs(Vo)))
+    np.testing.assert_allclose(Vg, Vo, rtol=0, atol=1e-9 * scale)
+    b = O.policy_cost(mdp, pi)
+    assert np.max(np.abs(b - O.j_apply(mdp, pi, Vg))) <= alpha * np.max(np.abs(b)) * (1 + 1e-9)
+
+
+def test_eval_mixed_widest_fused_passes_past_two_grid_strides():
+    """Mixed path (FP32 basis) at n = 300007 (threads take two or three rows,
+    ragged tail) with W = 64 and a tight rule, so that cycles run into the
+    48- and 64-column fused passes; the FP64 residual on the stored MDP
+    decides the stop, so the rule holds exactly there, and the error from
+    the policy's value is at most ||residual||_inf / (1 - gamma)."""
+    n, W, alpha = 300007, 64, 1e-9
+    mdp = synth.sparse_band(n, 2, 8, 0.995, seed=6)
+    stored = mdp.with_values(val=synth.upcast_values(synth.round_values(mdp.val, "fp32"), "fp32"))
+    pi = np.random.default_rng(6).integers(0, 2, size=n).astype(np.int32)
+    Vg, st = gpu_eval(mdp, pi, np.zeros(n), alpha, W, store="fp32", mode="mixed")
+    print(f"mixed n={n}: inner={st['inner']} restarts={st['restarts']}")
+    assert st["status"] == 0 and st["converged"] == 1
+    # some cycle is at least this long, so it ran through columns 32..48 and past 48
+    assert -(-st["inner"] // (st["restarts"] + 1)) > 48, st
+    b = O.policy_cost(stored, pi)
+    res = np.max(np.abs(b - O.j_apply(stored, pi, Vg)))
+    assert res <= alpha * np.max(np.abs(b)) * (1 + 1e-9)
