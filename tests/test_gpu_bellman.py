@@ -118,3 +118,15 @@ def test_bellman_dense_action_groups(m, store, sets):
     if sets:
         mdp = synth.with_action_sets(mdp, 0.5, 12 + m)
     check(mdp, np.random.default_rng(m).normal(size=n) * 5, store=store)
+
+
+@pytest.mark.parametrize("name,store", [("c4", "fp32"), ("c3", "fp32"), ("c3", "bf16")])
+def test_bellman_full_size(name, store):
+    """The full c3 (dense, n = 1e4, m = 4) and c4 (sparse, n = 4e6, m = 8,
+    k = 16) workloads through the kernels and launch shapes the bench times,
+    every state against the FP64 oracle's Bellman operator on the stored
+    values, for a V on the scale of V* (costs in [0, 1)).  Dense rows sum
+    1e4 products, so their tolerance allows for a different summation order."""
+    mdp = synth.config(name, seed=0)
+    V = np.random.default_rng(3).uniform(0.0, 1.0 / (1.0 - mdp.gamma), size=mdp.n)
+    check(mdp, V, store=store, rtol=1e-12 if mdp.fmt == "dense" else 1e-14)
