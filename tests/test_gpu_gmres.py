@@ -133,3 +133,20 @@ def test_eval_mixed_widest_fused_passes_past_two_grid_strides():
     b = O.policy_cost(stored, pi)
     res = np.max(np.abs(b - O.j_apply(stored, pi, Vg)))
     assert res <= alpha * np.max(np.abs(b)) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("alpha,W", [(1e-6, 30), (1e-12, 3), (1e-9, 2)])
+def test_eval_dense_c3_full_size_matches_literal_algorithm(alpha, W):
+    """Dense P^pi products at the full c3 size (n = 1e4, FP64): the same
+    stopping step, restarts and iterate as the literal algorithm, with and
+    without restarts (W = 2 restarts 24 times)."""
+    mdp = synth.config("c3", seed=0)
+    pi = np.random.default_rng(7).integers(0, mdp.m, size=mdp.n).astype(np.int32)
+    x0 = np.zeros(mdp.n)
+    Vg, st = gpu_eval(mdp, pi, x0, alpha, W)
+    Vo, info = O.gmres_inner(mdp, pi, x0, alpha, W)
+    assert st["status"] == 0 and st["converged"] == 1
+    assert st["inner"] == info["steps"], (st, info["steps"])
+    assert st["restarts"] == info["restarts"]
+    scale = max(1.0, np.max(np.abs(Vo)))
+    np.testing.assert_allclose(Vg, Vo, rtol=0, atol=1e-9 * scale)
