@@ -168,6 +168,20 @@ def test_serving_errors_and_v0():
         assert np.array_equal(V2, V) and np.array_equal(pi2, pi)
 
 
+def test_serving_arena_beyond_device_memory():
+    """An arena larger than the device's memory: srv_create reports
+    IG_E_NOMEM (the failed allocation leaves no error behind), and a server
+    with an ordinary arena serves a request afterwards."""
+    I = igm()
+    with pytest.raises(I.IgError) as ei:
+        I.Server(hbm_budget=1 << 50)
+    assert ei.value.status == I.IG_E_NOMEM
+    good = request_mdp(MIX[0])
+    with I.Server(max_states=50000) as srv:
+        V, pi, st = srv.result(srv.submit(good, params(good)))
+    certify(good, V, pi, st)
+
+
 def test_serving_action_sets_match_direct_solve():
     """Requests with state-dependent action sets (excluded rows empty, their
     costs NaN) are served like any other: bitwise the direct persistent
