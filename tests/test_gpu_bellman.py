@@ -48,7 +48,8 @@ def check(mdp, V, store="fp64", rtol=1e-14):
 
 
 @pytest.mark.parametrize("n,m,k", [(1, 1, 1), (1, 3, 1), (63, 2, 4), (64, 4, 5), (65, 4, 5),
-                                   (100, 4, 5), (777, 3, 7), (2000, 8, 20), (130, 17, 3)])
+                                   (100, 4, 5), (777, 3, 7), (2000, 8, 20), (130, 17, 3),
+                                   (300, 300, 3), (70, 1000, 2)])
 def test_bellman_shapes(n, m, k):
     mdp = synth.sparse_uniform(n, m, min(k, n), 0.9, seed=n + m)
     V = np.random.default_rng(1).normal(size=n) * 5
@@ -130,3 +131,10 @@ def test_bellman_full_size(name, store):
     mdp = synth.config(name, seed=0)
     V = np.random.default_rng(3).uniform(0.0, 1.0 / (1.0 - mdp.gamma), size=mdp.n)
     check(mdp, V, store=store, rtol=1e-12 if mdp.fmt == "dense" else 1e-14)
+
+
+@pytest.mark.parametrize("store", ["fp64", "fp32", "bf16"])
+def test_bellman_dense_many_actions(store):
+    """Dense rows with 200 actions per state (50 groups of four actions)."""
+    mdp = synth.dense_exp(64, 200, 0.95, seed=3)
+    check(mdp, np.random.default_rng(9).normal(size=64) * 5, store=store)

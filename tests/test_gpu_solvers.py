@@ -348,3 +348,16 @@ def test_other_solvers_dense(method, store):
     assert st["converged"] == 1
     assert rel_err(V, Vs) <= (1e-8 if store == "fp64" else 1e-6)
     assert_policy_match(stored, Vs, pis, pi)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n,m,k", [(300, 300, 3), (70, 1000, 2)])
+def test_many_actions(n, m, k, engine):
+    """Hundreds of actions per state (300 and 1000: rows of many actions per
+    ELL slice and long per-state argmin chains): V* and pi* of PI with LU."""
+    mdp = synth.sparse_uniform(n, m, k, 0.95, seed=m)
+    Vs, pis, _ = O.policy_iteration(mdp)
+    V, pi, st = solve(mdp, tol=tol_par(mdp, np.max(np.abs(Vs))), engine=engine)
+    assert st["converged"] == 1
+    assert rel_err(V, Vs) <= 1e-8
+    assert_policy_match(mdp, Vs, pis, pi)
