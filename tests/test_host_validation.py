@@ -136,3 +136,12 @@ def test_refine_needs_bf16_store_and_wider_input():
     assert "refine" in expect_invalid(m, store="fp32", refine=True)
     m16 = m.with_values(val=synth.round_values(m.val, "bf16"))
     assert "refine" in expect_invalid(m16, store="bf16", refine=True)
+
+
+def test_empty_problem():
+    """No states or no actions: rejected before any device work."""
+    import dataclasses
+    b = base()
+    empty = dict(row_ptr=np.zeros(1, np.int64), col=np.zeros(0, np.int32), val=np.zeros(0))
+    assert "n >= 1" in expect_invalid(dataclasses.replace(b, n=0, cost=np.zeros(0), **empty))
+    assert "m >= 1" in expect_invalid(dataclasses.replace(b, m=0, cost=np.zeros(0), **empty))
