@@ -309,9 +309,16 @@ ig_status ipi_vi_solve(ig_mdp_t mdp, double* V, int32_t* pi, const ig_params* pa
  * persistent launch of a whole solve.  mask 0 disables. */
 #define IG_PROFILE_CLASSES 8
 ig_status ig_profile_enable(ig_mdp_t mdp, unsigned mask);
-/* Sum of event-timed milliseconds and launch counts per class since the last
- * reset (synchronises on the recorded events).  ms and launches have
- * IG_PROFILE_CLASSES entries (host memory). */
+/* Sampling of the bracketed launches: with every = k only the first launch of
+ * each enabled class and then one in every k are bracketed (default 1: all),
+ * so that the events' own cost stays out of a timed run while every sampled
+ * launch is still timed on its stream.  Restarts the per-class launch counts
+ * (as do ig_profile_enable and a reset of ig_profile_read).  IG_E_INVALID for
+ * every < 1. */
+ig_status ig_profile_sample(ig_mdp_t mdp, int every);
+/* Sum of event-timed milliseconds and counts of timed launches per class
+ * since the last reset (synchronises on the recorded events).  ms and
+ * launches have IG_PROFILE_CLASSES entries (host memory). */
 ig_status ig_profile_read(ig_mdp_t mdp, double* ms, int64_t* launches, int reset);
 
 /* ---- Continuous-batching serving ------------------------------------------

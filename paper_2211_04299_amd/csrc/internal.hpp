@@ -127,6 +127,8 @@ struct Mdp {
   unsigned prof_mask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[KC_COUNT];
   size_t prof_used[KC_COUNT] = {0};
+  uint32_t prof_every = 1;                 // bracket one launch in prof_every per class
+  uint64_t prof_seen[KC_COUNT] = {0};      // launches of each class since the counters restarted
   double cost_max = 0;  // max |g(s, a)|
 };
 

@@ -30,6 +30,7 @@ ig_status sync_status(Mdp& d, hipStream_t s) {
 
 ProfScope::ProfScope(Mdp& d_, KClass k_, hipStream_t s_) : d(d_), k(k_), s(s_) {
   if (!(d.prof_mask & (1u << k))) return;
+  if (d.prof_seen[k]++ % d.prof_every != 0) return;  // not one of the sampled launches
   auto& pool = d.prof_ev[k];
   if (d.prof_used[k] == pool.size()) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -1017,6 +1018,15 @@ ig_status mdp_get_info(ig_mdp_t mdp, ig_mdp_info* info) {
 ig_status ig_profile_enable(ig_mdp_t mdp, unsigned mask) {
   if (!mdp) return ig::fail(IG_E_INVALID, "NULL handle");
   mdp->d.prof_mask = mask;
+  for (auto& c : mdp->d.prof_seen) c = 0;
+  return IG_OK;
+}
+
+ig_status ig_profile_sample(ig_mdp_t mdp, int every) {
+  if (!mdp) return ig::fail(IG_E_INVALID, "NULL handle");
+  if (every < 1) return ig::fail(IG_E_INVALID, "every must be >= 1");
+  mdp->d.prof_every = (uint32_t)every;
+  for (auto& c : mdp->d.prof_seen) c = 0;
   return IG_OK;
 }
 
@@ -1035,7 +1045,10 @@ ig_status ig_profile_read(ig_mdp_t mdp, double* ms, int64_t* launches, int reset
     }
     ms[k] = tot;
     launches[k] = (int64_t)d.prof_used[k];
-    if (reset) d.prof_used[k] = 0;
+    if (reset) {
+      d.prof_used[k] = 0;
+      d.prof_seen[k] = 0;
+    }
   }
   return IG_OK;
 }

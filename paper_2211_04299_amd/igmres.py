@@ -37,8 +37,8 @@ PROFILE_CLASS_NAMES = ["bellman", "japply", "gram_schmidt", "update", "residual"
 
 EXPORTS = ["ig_params_default", "mdp_create", "mdp_destroy", "mdp_get_info", "bellman_apply",
            "policy_eval_gmres", "igmres_pi_solve", "pi_solve", "opi_solve", "ipi_vi_solve",
-           "igmres_pi_solve_noalloc", "ig_profile_enable", "ig_profile_read", "ig_last_error",
-           "ig_server_config_default",
+           "igmres_pi_solve_noalloc", "ig_profile_enable", "ig_profile_sample", "ig_profile_read",
+           "ig_last_error", "ig_server_config_default",
            "srv_create", "srv_submit", "srv_poll", "srv_result", "srv_get_info", "srv_destroy"]
 
 
@@ -106,6 +106,7 @@ _sig = {
     "opi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
     "ipi_vi_solve": (C.c_int, [_P, _P, _P, C.POINTER(Params), C.POINTER(Stats), _P]),
     "ig_profile_enable": (C.c_int, [_P, C.c_uint]),
+    "ig_profile_sample": (C.c_int, [_P, C.c_int]),
     "ig_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
     "ig_last_error": (C.c_char_p, []),
     "ig_server_config_default": (None, [C.POINTER(ServerConfig)]),
@@ -234,6 +235,9 @@ class Mdp:
     # ---- measurement ------------------------------------------------------
     def profile_enable(self, mask: int):
         _check(_lib.ig_profile_enable(self.handle, mask), "ig_profile_enable")
+
+    def profile_sample(self, every: int):
+        _check(_lib.ig_profile_sample(self.handle, int(every)), "ig_profile_sample")
 
     def profile_read(self, reset=True):
         ms = (C.c_double * IG_PROFILE_CLASSES)()
