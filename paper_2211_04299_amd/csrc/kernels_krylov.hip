@@ -33,6 +33,7 @@ constexpr int kFinT = 1024;  // threads of the finishing kernel
 constexpr int kGsT = 512;    // threads per block of the fused Gram-Schmidt passes
 constexpr int kGsB = 256;    // their grid cap (as many threads as 512 blocks of 256)
 constexpr int kFinBatch = 16;  // partial rows each finishing thread loads at once
+constexpr int kUpdStage = 64;  // columns of R the solution update stages in LDS
 
 template <typename XT>
 __device__ __forceinline__ const XT* qcol(const XT* Q, int64_t n, int j) {
@@ -420,11 +421,24 @@ __global__ __launch_bounds__(kBlock) void k_update(const XT* __restrict__ Q, int
                                                    const double* __restrict__ Vb,
                                                    double* __restrict__ V) {
   __shared__ double y[kMaxW];
+  // up to kUpdStage columns: the triangle of R (column l holds rows 0..l,
+  // packed) and g are loaded into LDS by the whole block in one round trip,
+  // so that the serial back substitution reads LDS, not device memory
+  __shared__ double Rs[kUpdStage * (kUpdStage + 1) / 2], gsh[kUpdStage];
+  const bool staged = i <= kUpdStage;
+  if (staged) {
+    for (int l = threadIdx.x / 64; l < i; l += kBlock / 64)
+      for (int j = threadIdx.x % 64; j <= l; j += 64)
+        Rs[l * (l + 1) / 2 + j] = gs->R[(int64_t)l * (kMaxW + 1) + j];
+    for (int j = threadIdx.x; j < i; j += kBlock) gsh[j] = gs->g[j];
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     for (int j = i - 1; j >= 0; --j) {
-      double acc = gs->g[j];
-      for (int l = j + 1; l < i; ++l) acc -= gs->R[(int64_t)l * (kMaxW + 1) + j] * y[l];
-      const double dj = gs->R[(int64_t)j * (kMaxW + 1) + j];
+      double acc = staged ? gsh[j] : gs->g[j];
+      for (int l = j + 1; l < i; ++l)
+        acc -= (staged ? Rs[l * (l + 1) / 2 + j] : gs->R[(int64_t)l * (kMaxW + 1) + j]) * y[l];
+      const double dj = staged ? Rs[j * (j + 1) / 2 + j] : gs->R[(int64_t)j * (kMaxW + 1) + j];
       y[j] = dj != 0.0 ? acc / dj : 0.0;
     }
   }
@@ -432,12 +446,20 @@ __global__ __launch_bounds__(kBlock) void k_update(const XT* __restrict__ Q, int
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += stride) {
     double v0 = Vb ? Vb[s] : 0.0, v1 = 0.0;
-    int j = 0;
-    for (; j + 2 <= i; j += 2) {
-      v0 = fma(y[j], to_d(qcol(Q, n, j)[s]), v0);
-      v1 = fma(y[j + 1], to_d(qcol(Q, n, j + 1)[s]), v1);
+    // the columns in batches of 16 whose loads are issued together (the
+    // last batch re-reads its last column, clamped); even columns sum into
+    // v0 and odd ones into v1, each in increasing order
+    for (int j = 0; j < i; j += 16) {
+      const int rem = min(16, i - j);
+      XT q[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) q[k] = qcol(Q, n, j + min(k, rem - 1))[s];
+#pragma unroll
+      for (int k = 0; k < 16; k += 2) {
+        if (k < rem) v0 = fma(y[j + k], to_d(q[k]), v0);
+        if (k + 1 < rem) v1 = fma(y[j + k + 1], to_d(q[k + 1]), v1);
+      }
     }
-    if (j < i) v0 = fma(y[j], to_d(qcol(Q, n, j)[s]), v0);
     V[s] = v0 + v1;
   }
 }
