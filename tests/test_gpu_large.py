@@ -19,7 +19,7 @@ def igm():
     return igmres
 
 
-def solve_certified(mdp, store, tol, restart, mode="mixed"):
+def solve_certified(mdp, store, tol, restart, mode="mixed", engine=0):
     I = igm()
     if mdp.fmt == "csr":
         stored = mdp.with_values(val=synth.round_values(mdp.val, store))
@@ -30,7 +30,8 @@ def solve_certified(mdp, store, tol, restart, mode="mixed"):
     with I.mdp_create(stored, store=store) as h:
         V = zeros(mdp.n)
         pi = zeros(mdp.n, "int32")
-        st = h.igmres_pi_solve(V, pi, I.params_default(mdp.gamma, tol=tol, restart=restart, mode=mode))
+        st = h.igmres_pi_solve(V, pi, I.params_default(mdp.gamma, tol=tol, restart=restart, mode=mode,
+                                                       engine=engine))
         Vh, pih = host(V), host(pi)
     TV, pio, res = O.bellman(ref, Vh)
     return Vh, pih, st, ref, TV, pio, res
@@ -117,3 +118,15 @@ def test_persistent_engine_at_its_largest_shape():
         Vb, pib = host(V), host(pi)
     TV, pio, res = O.bellman(big, Vb)
     check(big, Vb, pib, st, big, TV, pio, res, tol)
+
+
+@pytest.mark.parametrize("store", ["fp32", "bf16"])
+def test_stream_engine_ragged_large_solve(store):
+    """The stream engine's whole solve at n = 200003 (the last ELL slice and
+    the last grid stride of every pass ragged), banded plus uniform
+    successors as c4, mixed precision (the automatic choice would take the
+    persistent engine at this size); checked by the certificate against the
+    FP64 oracle's Bellman operator on the stored MDP."""
+    mdp = synth.sparse_band(200003, 4, 12, 0.99, seed=21)
+    out = solve_certified(mdp, store, tol=1e-8, restart=30, engine=1)
+    check(mdp, *out, tol=1e-8)
